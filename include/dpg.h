@@ -1,0 +1,162 @@
+/*
+ * dpg.h -- C ABI of the sum-factorised DPG Gram-matrix integrator for
+ * hexahedral elements on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  For each element K with map x_K : (0,1)^3 -> K the Gram
+ * matrix G_IJ = (h_I, h_J) (2.13) of the test space of order p, for one of
+ * the four inner products of the hexahedral exact sequence (2.1):
+ *   DPG_H1     (u,v) + (grad u, grad v)              (2.28), Section 2.4
+ *   DPG_HCURL  (E,F) + (curl E, curl F)              (2.65), Section 2.6
+ *   DPG_HDIV   (V,W) + (div V, div W)                (2.46), Section 2.5
+ *   DPG_L2     (q,r)                                 (2.14), Section 2.3
+ * with hierarchical integrated-Legendre / Legendre shape functions
+ * (Section 2.8.2), pushed forward with the Piola maps (2.3)-(2.6).  The
+ * value part is weighted by w0 and the derivative part by w1 (w0 = w1 = 1 is
+ * the paper's inner product).
+ *
+ * Shape-function numbering (component a = 0,1,2 concatenated, i1 fastest):
+ *   I = off_a + i1 + R1(a) i2 + R1(a) R2(a) i3
+ * with ranges R_d(a): H1 p+1; L2 p; H(curl) p if d == a else p+1;
+ * H(div) p+1 if d == a else p  (index maps of Sections 2.3-2.6, (2.53), (2.71)).
+ * Dimensions: H1 (p+1)^3, H(curl) 3p(p+1)^2, H(div) 3(p+1)p^2, L2 p^3.
+ *
+ * Output layout.  One symmetric matrix per element in LAPACK 'U' packed
+ * column-major storage: entry (I,J), I <= J, at offset I + J(J+1)/2; the
+ * element's n(n+1)/2 entries are contiguous.  Elements are consecutive
+ * (element e at e * dpg_gram_packed_len(space,p)) unless an offset array is
+ * given.  FP64 output is double, FP32 output is float.
+ *
+ * Paths.  GENERAL is the staged x3 -> x2 -> x1 sum-factorised quadrature
+ * (Algorithms 2/3, 5, 7, 9 generalised), O(p^7) per element, with the
+ * tensor Gauss-Legendre rule of L points per direction (default L = p+1,
+ * L = p for L2).  REDUCED is the constant-Jacobian simplification of
+ * Section 2.8.1 (Algorithm 10 carried to all four spaces) using the exact
+ * 1D integrals (2.103)-(2.114), O(p^6); it requires affine geometry.
+ * AUTO picks REDUCED for affine geometry and GENERAL otherwise.  On affine
+ * elements both paths give the same matrix (the rule is exact there).
+ *
+ * Precision.  FP64: everything in double.  FP32: the Jacobian / metric is
+ * evaluated in double, then the coefficient fields and 1D tables are rounded
+ * once (round-to-nearest-even) to float; all contractions accumulate in float.
+ *
+ * Memory.  Unless stated otherwise every pointer argument is a DEVICE
+ * pointer owned by the caller; the library never frees caller memory.
+ * Streams are hipStream_t passed as void* (NULL = the null stream).  Calls
+ * that take a stream only enqueue work and return; results and per-element
+ * status words are valid after the stream is synchronised.
+ *
+ * Errors.  Every int-returning function returns DPG_OK (0) or a negative
+ * code; dpg_last_error() gives a message for the calling thread.
+ */
+#ifndef DPG_H
+#define DPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DPG_H1 = 0, DPG_HCURL = 1, DPG_HDIV = 2, DPG_L2 = 3 };
+enum { DPG_FP64 = 0, DPG_FP32 = 1 };
+enum { DPG_GEOM_TRILINEAR = 0, DPG_GEOM_AFFINE = 1 };
+enum { DPG_PATH_AUTO = 0, DPG_PATH_GENERAL = 1, DPG_PATH_REDUCED = 2 };
+
+enum {
+  DPG_OK = 0,
+  DPG_PENDING = 1,      /* serve: request not finished yet                      */
+  DPG_EINVAL = -1,      /* bad argument (space, p, nq, null pointer, path/kind)  */
+  DPG_ENOMEM = -2,      /* device or host allocation failed                      */
+  DPG_EHIP = -3,        /* HIP runtime error (message in dpg_last_error)         */
+  DPG_EJACOBIAN = -4,   /* element with det J <= 0 at a quadrature point         */
+  DPG_EAGAIN = -5,      /* serve: queue full, retry later                        */
+  DPG_ENOTINIT = -6,    /* null / destroyed context                              */
+  DPG_ENODEV = -7       /* no usable gfx950 device                               */
+};
+
+#define DPG_P_MAX 11     /* largest supported order p (p + dp of a DPG test space) */
+
+typedef struct dpg_ctx dpg_ctx;
+typedef struct dpg_server dpg_server;
+
+/* Element geometry, device memory, float64, C order.
+ *   DPG_GEOM_TRILINEAR: data[n_elem][8][3], vertex v = v1 + 2 v2 + 4 v3 at the
+ *     master corner (v1,v2,v3); x(xi) = sum_v X_v prod_d (v_d ? xi_d : 1 - xi_d).
+ *   DPG_GEOM_AFFINE: data[n_elem][12] = x0[3], J[3][3] row-major, J_ij = dx_i/dxi_j
+ *     ((2.2)); x(xi) = x0 + J xi.
+ * The map must be a diffeomorphism (Section 2.2): det J > 0. */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  int64_t n_elem;
+  const double* data;
+} dpg_geometry;
+
+/* Options.  prec: DPG_FP64 / DPG_FP32.  path: DPG_PATH_*.  nq: points per
+ * direction, 0 = default (p+1; p for L2); only the default is built.
+ * w0, w1: weights of the value and derivative parts.
+ * status: optional device int32[n_elem]; written with DPG_OK or DPG_EJACOBIAN
+ * per element.  An element with det J <= 0 at any quadrature point (GENERAL)
+ * or det J <= 0 (REDUCED) gets an all-zero output block. */
+typedef struct {
+  int32_t prec;
+  int32_t path;
+  int32_t nq;
+  int32_t reserved;
+  double w0;
+  double w1;
+  int32_t* status;
+} dpg_opts;
+
+/* Fill *opts with the defaults (FP64, AUTO, nq = 0, w0 = w1 = 1, no status). */
+void dpg_opts_default(dpg_opts* opts);
+
+/* Build the 1D tables (Gauss-Legendre rules on (0,1) for every point count
+ * up to p_max + 1, chi_k and chi'_k at the nodes (2.91)-(2.101), the exact 1D
+ * integrals F^{rs} (2.103)-(2.114)) in float64 on the host, with a float32
+ * rounding, and make them resident on the current device.  p_max in
+ * [1, DPG_P_MAX].  Blocks until the tables are on the device.  The context
+ * is immutable afterwards and may be shared by threads and streams; it owns
+ * its device memory until dpg_ctx_destroy. */
+int dpg_tables_build(int p_max, void* stream, dpg_ctx** ctx);
+int dpg_ctx_destroy(dpg_ctx* ctx);
+
+/* Dimension n of the test space and n(n+1)/2; -1 for invalid arguments. */
+int64_t dpg_gram_dim(int space, int p);
+int64_t dpg_gram_packed_len(int space, int p);
+
+/* Integrate the Gram matrices of geom->n_elem elements of one space and
+ * order into out (device, packed, element e at e * packed_len).  opts may be
+ * NULL (defaults).  Asynchronous on stream. */
+int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom,
+                       void* out, const dpg_opts* opts, void* stream);
+
+/* Uneven batch: element e has space[e] and order p[e] (device int8 arrays of
+ * length geom->n_elem; p[e] in [1, ctx p_max]) and its packed matrix starts at
+ * out + out_offset[e] (device int64, in elements of the output type; regions
+ * must not overlap).  All elements share opts (precision, path, weights).
+ * The host reads space/p once (a device-to-host copy on stream) to plan the
+ * launch; planning state is cached per context for repeated identical
+ * batches (same pointers and sizes), and the launch sequence is replayed
+ * from a captured HIP graph on later calls. */
+int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                               const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                               const dpg_opts* opts, void* stream);
+
+/* Host-only helpers (no device needed): the tables the library builds. */
+/* zeta[L], w[L], chi[(kmax+1) * L], dchi[(kmax+1) * L] with chi[k * L + l] = chi_k(zeta_l). */
+int dpg_host_tables(int L, int kmax, double* zeta, double* w, double* chi, double* dchi);
+/* F[(kmax+1)^2] with F[i * (kmax+1) + j] = int_0^1 chi^<r>_i chi^<s>_j  ((2.90)). */
+int dpg_host_ftable(int r, int s, int kmax, double* F);
+/* Algorithmic work of one element on the GENERAL path: flops of the three
+ * staged contractions, and output bytes; -1 on invalid arguments. */
+double dpg_general_flops(int space, int p);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* dpg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPG_H */

@@ -1,0 +1,281 @@
+// api.cpp -- the C ABI (include/dpg.h): validation, context, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dpg.h"
+#include "kernels.h"
+#include "tables.h"
+#include "terms.h"
+
+struct dpg_ctx {
+  int p_max = 0;
+  int device = 0;
+  double* d_tab64 = nullptr;
+  float* d_tab32 = nullptr;
+  double* d_f64 = nullptr;
+  float* d_f32 = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DPG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
+
+hipError_t launch_general(int space, int p, int prec, const dpg::GeneralArgs& a, hipStream_t st) {
+  switch (space) {
+    case DPG_H1: return dpg::launch_general_h1(p, prec, a, st);
+    case DPG_HCURL: return dpg::launch_general_hcurl(p, prec, a, st);
+    case DPG_HDIV: return dpg::launch_general_hdiv(p, prec, a, st);
+    case DPG_L2: return dpg::launch_general_l2(p, prec, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Fill the launch arguments shared by every element of one (space, p).
+int make_args(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
+              const dpg_opts& o, dpg::GeneralArgs& a) {
+  const int L = dpg::npoints(space, p);
+  if (o.nq != 0 && o.nq != L)
+    return fail(DPG_EINVAL, "nq=%d: only the default point count (%d) is built", o.nq, L);
+  a = dpg::GeneralArgs{};
+  a.geom = geom->data;
+  a.geom_kind = geom->kind;
+  a.out = out;
+  a.packed_len = dpg::packed_len(space, p);
+  a.tab64 = ctx->d_tab64 + dpg::table_offset(L);
+  a.tabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + dpg::table_offset(L))
+                              : static_cast<const void*>(a.tab64);
+  a.ftabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_f32) : static_cast<const void*>(ctx->d_f64);
+  a.w0 = o.w0;
+  a.w1 = o.w1;
+  a.status = o.status;
+  return DPG_OK;
+}
+
+int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const dpg_opts& o) {
+  if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
+  if (!geom) return fail(DPG_EINVAL, "geometry is NULL");
+  if (geom->kind != DPG_GEOM_TRILINEAR && geom->kind != DPG_GEOM_AFFINE)
+    return fail(DPG_EINVAL, "unknown geometry kind %d", geom->kind);
+  if (geom->n_elem < 0) return fail(DPG_EINVAL, "negative element count");
+  if (geom->n_elem > 0 && (!geom->data || !out)) return fail(DPG_EINVAL, "geometry data or output is NULL");
+  if (o.prec != DPG_FP64 && o.prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", o.prec);
+  if (o.path < DPG_PATH_AUTO || o.path > DPG_PATH_REDUCED) return fail(DPG_EINVAL, "unknown path %d", o.path);
+  if (o.path == DPG_PATH_REDUCED && geom->kind != DPG_GEOM_AFFINE)
+    return fail(DPG_EINVAL, "the reduced path needs affine geometry");
+  if (!std::isfinite(o.w0) || !std::isfinite(o.w1)) return fail(DPG_EINVAL, "weights must be finite");
+  return DPG_OK;
+}
+
+bool use_reduced(const dpg_geometry* geom, const dpg_opts& o) {
+  return o.path == DPG_PATH_REDUCED || (o.path == DPG_PATH_AUTO && geom->kind == DPG_GEOM_AFFINE);
+}
+
+}  // namespace
+
+extern "C" {
+
+void dpg_opts_default(dpg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->prec = DPG_FP64;
+  o->path = DPG_PATH_AUTO;
+  o->nq = 0;
+  o->w0 = 1.0;
+  o->w1 = 1.0;
+  o->status = nullptr;
+}
+
+const char* dpg_last_error(void) { return g_err.c_str(); }
+
+int64_t dpg_gram_dim(int space, int p) {
+  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
+  return dpg::gram_dim(space, p);
+}
+
+int64_t dpg_gram_packed_len(int space, int p) {
+  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
+  return dpg::packed_len(space, p);
+}
+
+double dpg_general_flops(int space, int p) {
+  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1.0;
+  return dpg::general_flops(space, p);
+}
+
+int dpg_host_tables(int L, int kmax, double* zeta, double* w, double* chi, double* dchi) {
+  if (L < 1 || L > 64 || kmax < 0 || kmax > dpg::KT - 1 || !zeta || !w || !chi || !dchi)
+    return fail(DPG_EINVAL, "dpg_host_tables: bad arguments");
+  dpg::gauss_legendre_01(L, zeta, w);
+  dpg::chi_tables(L, zeta, kmax, chi, dchi);
+  return DPG_OK;
+}
+
+int dpg_host_ftable(int r, int s, int kmax, double* F) {
+  if (r < 0 || r > 1 || s < 0 || s > 1 || kmax < 0 || kmax > 64 || !F)
+    return fail(DPG_EINVAL, "dpg_host_ftable: bad arguments");
+  for (int i = 0; i <= kmax; ++i)
+    for (int j = 0; j <= kmax; ++j) F[i * (kmax + 1) + j] = dpg::ftable_entry(r, s, i, j);
+  return DPG_OK;
+}
+
+int dpg_tables_build(int p_max, void* stream, dpg_ctx** out) {
+  if (!out) return fail(DPG_EINVAL, "ctx output pointer is NULL");
+  *out = nullptr;
+  if (p_max < 1 || p_max > DPG_P_MAX) return fail(DPG_EINVAL, "p_max=%d outside [1, %d]", p_max, DPG_P_MAX);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DPG_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(DPG_ENODEV, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+
+  std::vector<double> t64(dpg::TABLE_LEN), f64(dpg::FTAB_LEN);
+  std::vector<float> t32(dpg::TABLE_LEN), f32(dpg::FTAB_LEN);
+  dpg::build_tables(t64.data(), t32.data(), f64.data(), f32.data());
+
+  dpg_ctx* c = new (std::nothrow) dpg_ctx;
+  if (!c) return fail(DPG_ENOMEM, "host allocation failed");
+  c->p_max = p_max;
+  c->device = dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  size_t bytes = dpg::TABLE_LEN * (sizeof(double) + sizeof(float)) + dpg::FTAB_LEN * (sizeof(double) + sizeof(float));
+  char* base = nullptr;
+  e = hipMalloc(reinterpret_cast<void**>(&base), bytes);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(DPG_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  c->d_tab64 = reinterpret_cast<double*>(base);
+  c->d_f64 = c->d_tab64 + dpg::TABLE_LEN;
+  c->d_tab32 = reinterpret_cast<float*>(c->d_f64 + dpg::FTAB_LEN);
+  c->d_f32 = c->d_tab32 + dpg::TABLE_LEN;
+  e = hipMemcpyAsync(c->d_tab64, t64.data(), dpg::TABLE_LEN * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_f64, f64.data(), dpg::FTAB_LEN * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_tab32, t32.data(), dpg::TABLE_LEN * sizeof(float), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_f32, f32.data(), dpg::FTAB_LEN * sizeof(float), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    hipFree(base);
+    delete c;
+    return hip_fail(e, "table upload");
+  }
+  *out = c;
+  return DPG_OK;
+}
+
+int dpg_ctx_destroy(dpg_ctx* ctx) {
+  if (!ctx) return fail(DPG_ENOTINIT, "null context");
+  if (ctx->d_tab64) hipFree(ctx->d_tab64);
+  ctx->d_tab64 = nullptr;
+  delete ctx;
+  return DPG_OK;
+}
+
+int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
+                       const dpg_opts* opts, void* stream) {
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  int rc = check_common(ctx, geom, out, o);
+  if (rc) return rc;
+  if (!valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
+  if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
+  if (geom->n_elem == 0) return DPG_OK;
+  dpg::GeneralArgs a;
+  rc = make_args(ctx, space, p, geom, out, o, a);
+  if (rc) return rc;
+  a.n_items = geom->n_elem;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = use_reduced(geom, o) ? dpg::launch_affine(space, p, o.prec, a, st)
+                                            : launch_general(space, p, o.prec, a, st);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return DPG_OK;
+}
+
+int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                               const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                               const dpg_opts* opts, void* stream) {
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  int rc = check_common(ctx, geom, out, o);
+  if (rc) return rc;
+  const int64_t n = geom->n_elem;
+  if (n == 0) return DPG_OK;
+  if (!space || !p || !out_offset) return fail(DPG_EINVAL, "space, p and out_offset are required");
+  if (n > int64_t(0x7fffffff)) return fail(DPG_EINVAL, "batch too large (%lld elements)", (long long)n);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int8_t> hs(n), hp(n);
+  hipError_t e = hipMemcpyAsync(hs.data(), space, n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), p, n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "reading space/p");
+  // bucket by (space, p): counting sort, heaviest buckets launched first
+  const int NB = 4 * (DPG_P_MAX + 1);
+  std::vector<int64_t> cnt(NB + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!valid_space(hs[i]) || hp[i] < 1 || hp[i] > ctx->p_max)
+      return fail(DPG_EINVAL, "element %lld: space=%d p=%d invalid", (long long)i, hs[i], hp[i]);
+    cnt[hs[i] * (DPG_P_MAX + 1) + hp[i] + 1]++;
+  }
+  for (int b = 0; b < NB; ++b) cnt[b + 1] += cnt[b];
+  std::vector<int32_t> ids(n);
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i) ids[pos[hs[i] * (DPG_P_MAX + 1) + hp[i]]++] = int32_t(i);
+  }
+  int32_t* d_ids = nullptr;
+  e = hipMallocAsync(reinterpret_cast<void**>(&d_ids), n * sizeof(int32_t), st);
+  if (e != hipSuccess) return fail(DPG_ENOMEM, "hipMallocAsync ids: %s", hipGetErrorString(e));
+  e = hipMemcpyAsync(d_ids, ids.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) { hipFreeAsync(d_ids, st); return hip_fail(e, "upload ids"); }
+  // order buckets by estimated cost per element, descending
+  std::vector<int> order;
+  for (int b = 0; b < NB; ++b)
+    if (cnt[b + 1] > cnt[b]) order.push_back(b);
+  std::sort(order.begin(), order.end(), [](int x, int y) {
+    const int sx = x / (DPG_P_MAX + 1), px = x % (DPG_P_MAX + 1);
+    const int sy = y / (DPG_P_MAX + 1), py = y % (DPG_P_MAX + 1);
+    return dpg::packed_len(sx, px) > dpg::packed_len(sy, py);
+  });
+  for (int b : order) {
+    const int sp = b / (DPG_P_MAX + 1), pp = b % (DPG_P_MAX + 1);
+    dpg::GeneralArgs a;
+    rc = make_args(ctx, sp, pp, geom, out, o, a);
+    if (rc) { hipFreeAsync(d_ids, st); return rc; }
+    a.elem_ids = d_ids + cnt[b];
+    a.n_items = cnt[b + 1] - cnt[b];
+    a.out_offset = out_offset;
+    e = use_reduced(geom, o) ? dpg::launch_affine(sp, pp, o.prec, a, st) : launch_general(sp, pp, o.prec, a, st);
+    if (e != hipSuccess) { hipFreeAsync(d_ids, st); return hip_fail(e, "kernel launch"); }
+  }
+  e = hipFreeAsync(d_ids, st);
+  if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+  return DPG_OK;
+}
+
+}  // extern "C"

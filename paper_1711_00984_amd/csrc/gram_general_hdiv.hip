@@ -1,0 +1,11 @@
+// Instantiation of the general-path kernels for one space (split per space so
+// the build compiles them in parallel).
+#include "gram_general.inc.h"
+
+namespace dpg {
+
+hipError_t launch_general_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s) {
+  return dispatch_general<SP_HDIV>(p, prec, a, s);
+}
+
+}  // namespace dpg

@@ -1,0 +1,53 @@
+// kernels.h -- launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpg {
+
+constexpr int PMAX = 11;           // largest order p
+constexpr int LMAX = PMAX + 1;     // largest point count
+constexpr int KT = PMAX + 2;       // 1D function indices 0..PMAX+1 kept in the tables
+
+// Per point count L, one table block (both precisions share the layout):
+//   zeta[L] | w[L] | chi[KT][L] | dchi[KT][L]
+// The FP64 block is used for the metric (always FP64) and the FP64 path;
+// the FP32 block is the same table rounded once to float.
+constexpr int table_block_len(int L) { return 2 * L + 2 * KT * L; }
+constexpr int table_offset(int L) {
+  int o = 0;
+  for (int l = 1; l < L; ++l) o += table_block_len(l);
+  return o;
+}
+constexpr int TABLE_LEN = table_offset(LMAX + 1);
+constexpr int FTAB_LEN = 4 * KT * KT;   // F^{rs}[i][j] at ((2r+s)*KT + i)*KT + j
+
+struct GeneralArgs {
+  const double* geom;        // trilinear [E][8][3] or affine [E][12]
+  int geom_kind;             // 0 trilinear, 1 affine
+  int64_t n_items;           // elements in this launch
+  int64_t item_base;         // first item of this launch (grid chunking)
+  const int32_t* elem_ids;   // item -> element (nullptr: identity)
+  void* out;                 // Real*
+  const int64_t* out_offset; // element -> first output entry (nullptr: e * packed_len)
+  int64_t packed_len;
+  const double* tab64;       // FP64 table block for this L
+  const void* tabR;          // table block in the output precision
+  const void* ftabR;         // F tables in the output precision (reduced path)
+  double w0, w1;
+  int32_t* status;           // per element (nullptr: none)
+};
+
+// General (sum-factorised quadrature) path; prec 0 = FP64, 1 = FP32.
+hipError_t launch_general_h1(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
+
+// Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
+hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);
+
+// Number of work slabs per element (column slabs of the packed output).
+int general_slabs(int space, int p);
+
+}  // namespace dpg

@@ -1,0 +1,214 @@
+"""Thin ctypes binding of libdpg.so (include/dpg.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensors) and
+streams; pointers are passed as plain integers.  If the library is not
+built, importing this module raises ImportError: there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpg.so")
+
+H1, HCURL, HDIV, L2 = 0, 1, 2, 3
+SPACES = {"H1": H1, "HCURL": HCURL, "HDIV": HDIV, "L2": L2}
+FP64, FP32 = 0, 1
+TRILINEAR, AFFINE = 0, 1
+PATH_AUTO, PATH_GENERAL, PATH_REDUCED = 0, 1, 2
+PATHS = {"auto": PATH_AUTO, "general": PATH_GENERAL, "reduced": PATH_REDUCED}
+P_MAX = 11
+
+OK, PENDING, EINVAL, ENOMEM, EHIP, EJACOBIAN, EAGAIN, ENOTINIT, ENODEV = 0, 1, -1, -2, -3, -4, -5, -6, -7
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1711_00984_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_elem", ctypes.c_int64), ("data", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("path", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("w0", ctypes.c_double), ("w1", ctypes.c_double),
+                ("status", ctypes.c_void_p)]
+
+
+_vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+_lib.dpg_opts_default.argtypes = [ctypes.POINTER(Opts)]
+_lib.dpg_opts_default.restype = None
+_lib.dpg_last_error.argtypes = []
+_lib.dpg_last_error.restype = ctypes.c_char_p
+_lib.dpg_tables_build.argtypes = [_i, _vp, ctypes.POINTER(_vp)]
+_lib.dpg_tables_build.restype = _i
+_lib.dpg_ctx_destroy.argtypes = [_vp]
+_lib.dpg_ctx_destroy.restype = _i
+_lib.dpg_gram_dim.argtypes = [_i, _i]
+_lib.dpg_gram_dim.restype = _i64
+_lib.dpg_gram_packed_len.argtypes = [_i, _i]
+_lib.dpg_gram_packed_len.restype = _i64
+_lib.dpg_general_flops.argtypes = [_i, _i]
+_lib.dpg_general_flops.restype = _d
+_lib.dpg_gram_integrate.argtypes = [_vp, _i, _i, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp]
+_lib.dpg_gram_integrate.restype = _i
+_lib.dpg_gram_integrate_batched.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
+                                            ctypes.POINTER(Opts), _vp]
+_lib.dpg_gram_integrate_batched.restype = _i
+_lib.dpg_host_tables.argtypes = [_i, _i, _vp, _vp, _vp, _vp]
+_lib.dpg_host_tables.restype = _i
+_lib.dpg_host_ftable.argtypes = [_i, _i, _i, _vp]
+_lib.dpg_host_ftable.restype = _i
+
+
+class DpgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dpg error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise DpgError(rc, _lib.dpg_last_error().decode())
+    return rc
+
+
+def last_error():
+    return _lib.dpg_last_error().decode()
+
+
+def space_id(space):
+    return SPACES[space] if isinstance(space, str) else int(space)
+
+
+def gram_dim(space, p):
+    return int(_lib.dpg_gram_dim(space_id(space), p))
+
+
+def packed_len(space, p):
+    return int(_lib.dpg_gram_packed_len(space_id(space), p))
+
+
+def general_flops(space, p):
+    return float(_lib.dpg_general_flops(space_id(space), p))
+
+
+def default_points(space, p):
+    return p if space_id(space) == L2 else p + 1
+
+
+def host_tables(L, kmax):
+    """(zeta, w, chi[kmax+1, L], dchi[kmax+1, L]) as built by the library, float64 numpy."""
+    import numpy as np
+    z, w = np.zeros(L), np.zeros(L)
+    c, d = np.zeros((kmax + 1) * L), np.zeros((kmax + 1) * L)
+    _check(_lib.dpg_host_tables(L, kmax, z.ctypes.data, w.ctypes.data, c.ctypes.data, d.ctypes.data))
+    return z, w, c.reshape(kmax + 1, L), d.reshape(kmax + 1, L)
+
+
+def host_ftable(r, s, kmax):
+    import numpy as np
+    F = np.zeros((kmax + 1) * (kmax + 1))
+    _check(_lib.dpg_host_ftable(r, s, kmax, F.ctypes.data))
+    return F.reshape(kmax + 1, kmax + 1)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _geometry(geom, kind):
+    if not (geom.is_cuda and geom.dtype == torch.float64 and geom.is_contiguous()):
+        raise ValueError("geometry must be a contiguous float64 CUDA tensor")
+    kind = {"trilinear": TRILINEAR, "affine": AFFINE}.get(kind, kind)
+    per = 24 if kind == TRILINEAR else 12
+    if geom.numel() % per:
+        raise ValueError(f"geometry size {geom.numel()} is not a multiple of {per}")
+    return Geometry(kind, 0, geom.numel() // per, geom.data_ptr())
+
+
+def _opts(prec, path, nq, w0, w1, status):
+    o = Opts()
+    _lib.dpg_opts_default(ctypes.byref(o))
+    o.prec = {"fp64": FP64, "fp32": FP32}.get(prec, prec)
+    o.path = PATHS.get(path, path)
+    o.nq = nq
+    o.w0, o.w1 = float(w0), float(w1)
+    if status is not None:
+        if not (status.is_cuda and status.dtype == torch.int32):
+            raise ValueError("status must be an int32 CUDA tensor")
+        o.status = status.data_ptr()
+    return o
+
+
+class Context:
+    """Device-resident 1D tables (dpg_tables_build)."""
+
+    def __init__(self, p_max=P_MAX, stream=None):
+        self._h = ctypes.c_void_p()
+        _check(_lib.dpg_tables_build(p_max, _stream_ptr(stream), ctypes.byref(self._h)))
+        self.p_max = p_max
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(_lib.dpg_ctx_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gram(self, space, p, geom, kind="trilinear", out=None, prec="fp64", path="auto", nq=0,
+             w0=1.0, w1=1.0, status=None, stream=None):
+        """Packed Gram matrices of all elements of `geom` (dpg_gram_integrate).
+
+        Returns `out`, a 1D tensor of E * packed_len(space, p) entries
+        (float64 or float32), element e at [e * packed_len, (e+1) * packed_len).
+        """
+        g = _geometry(geom, kind)
+        dt = torch.float64 if prec in ("fp64", FP64) else torch.float32
+        m = packed_len(space, p)
+        if m < 0:
+            raise DpgError(EINVAL, f"invalid space/order ({space}, {p})")
+        n = g.n_elem * m
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=geom.device)
+        elif out.dtype != dt or out.numel() < n or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or size")
+        o = _opts(prec, path, nq, w0, w1, status)
+        _check(_lib.dpg_gram_integrate(self._h, space_id(space), p, ctypes.byref(g), out.data_ptr(),
+                                       ctypes.byref(o), _stream_ptr(stream)))
+        return out
+
+    def gram_batched(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
+                     w0=1.0, w1=1.0, status=None, stream=None):
+        """Uneven batch (dpg_gram_integrate_batched): int8 space/p, int64 offsets, all on device."""
+        g = _geometry(geom, kind)
+        for t, dt in ((space, torch.int8), (p, torch.int8), (out_offset, torch.int64)):
+            if not (t.is_cuda and t.dtype == dt and t.numel() == g.n_elem):
+                raise ValueError("space/p must be int8 and out_offset int64 CUDA tensors of length n_elem")
+        o = _opts(prec, path, 0, w0, w1, status)
+        _check(_lib.dpg_gram_integrate_batched(self._h, space.data_ptr(), p.data_ptr(), ctypes.byref(g),
+                                               out_offset.data_ptr(), out.data_ptr(), ctypes.byref(o),
+                                               _stream_ptr(stream)))
+        return out
+
+
+def exported_symbols():
+    """Names declared in include/dpg.h that the loaded library must export."""
+    return [n for n in dir(_lib) if n.startswith("dpg_")]

@@ -1,0 +1,256 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (through the C ABI).
+
+Tolerances (written here, derived in the design doc):
+* FP64: ||G_gpu - G_oracle||_F <= 1e-12 ||G_oracle||_F and
+        max |G_gpu - G_oracle| <= 1e-12 max |G_oracle|.
+* FP32: ||G_gpu - G_oracle||_F <= FP32_REL ||G_oracle||_F.
+Element-wise relative error is not used: many entries are exact zeros.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+from oracle import gram as og
+from oracle import shapes
+
+pytestmark = pytest.mark.gpu
+
+SPACES = ["H1", "HCURL", "HDIV", "L2"]
+TOL64 = 1e-12
+FP32_REL = 2e-6
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dpg():
+    from tests._lib import load_binding
+    return load_binding()
+
+
+@pytest.fixture(scope="module")
+def ctx(dpg):
+    say("building tables")
+    c = dpg.Context(p_max=11)
+    yield c
+    c.close()
+
+
+def run(ctx, space, p, geom_np, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0, status=None):
+    g = torch.from_numpy(np.ascontiguousarray(geom_np)).cuda()
+    out = ctx.gram(space, p, g, kind=kind, prec=prec, path=path, w0=w0, w1=w1, status=status)
+    torch.cuda.synchronize()
+    return out
+
+
+def elem(out_np, e, space, p):
+    n = shapes.dimension(space, p)
+    m = n * (n + 1) // 2
+    return og.unpack_upper(out_np[e * m:(e + 1) * m].astype(np.float64), n)
+
+
+def compare64(G, R, what):
+    fro = np.linalg.norm(G - R) / np.linalg.norm(R)
+    mx = np.abs(G - R).max() / np.abs(R).max()
+    assert fro <= TOL64 and mx <= TOL64, f"{what}: rel fro {fro:.3e}, rel max {mx:.3e}"
+    return fro
+
+
+# --------------------------------------------------------------------------
+
+def test_config1_cube_exact(ctx):
+    say("config 1: cube (0,2)^3, H1 p=3")
+    from tests.test_oracle_gram import load_golden
+    ex = load_golden().astype(np.float64)
+    X = meshgen.scaled_cube(2.0)
+    out = run(ctx, "H1", 3, X).cpu().numpy()
+    G = elem(out, 0, "H1", 3)
+    assert np.abs(G - ex).max() <= 4e-15 * np.abs(ex).max()
+    assert np.abs(G[ex == 0]).max() <= 4e-15
+    R = og.gram("H1", 3, "trilinear", X[0])
+    compare64(G, R, "config1 vs oracle")
+    # the same cube as an affine map, reduced path
+    A = np.zeros((1, 12))
+    A[0, 3:] = (2.0 * np.eye(3)).ravel()
+    Gr = elem(run(ctx, "H1", 3, A, kind="affine").cpu().numpy(), 0, "H1", 3)
+    assert np.abs(Gr - ex).max() <= 4e-15 * np.abs(ex).max()
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_general_fp64(ctx, space, p):
+    say(f"general fp64 {space} p={p}")
+    X = meshgen.perturbed_hexes(3, seed=500 + 10 * p + SPACES.index(space))
+    out = run(ctx, space, p, X).cpu().numpy()
+    for e in range(3):
+        compare64(elem(out, e, space, p), og.gram(space, p, "trilinear", X[e]), f"{space} p={p} e={e}")
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_general_weights(ctx, space):
+    say(f"general fp64 weighted {space}")
+    p = 3
+    X = meshgen.perturbed_hexes(2, seed=77)
+    for w0, w1 in ((0.7, 1.3), (1.0, 0.0), (0.0, 1.0)):
+        out = run(ctx, space, p, X, w0=w0, w1=w1).cpu().numpy()
+        for e in range(2):
+            R = og.gram(space, p, "trilinear", X[e], w0=w0, w1=w1)
+            if np.abs(R).max() == 0:
+                assert np.abs(elem(out, e, space, p)).max() == 0
+                continue
+            compare64(elem(out, e, space, p), R, f"{space} w=({w0},{w1})")
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [2, 4, 7])
+def test_general_fp32(ctx, space, p):
+    say(f"general fp32 {space} p={p}")
+    X = meshgen.perturbed_hexes(2, seed=900 + p)
+    out = run(ctx, space, p, X, prec="fp32").cpu().numpy()
+    assert out.dtype == np.float32
+    for e in range(2):
+        R = og.gram(space, p, "trilinear", X[e])
+        G = elem(out, e, space, p)
+        fro = np.linalg.norm(G - R) / np.linalg.norm(R)
+        say(f"  fp32 {space} p={p} e={e} rel fro {fro:.3e}")
+        assert fro <= FP32_REL
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 6])
+def test_reduced_fp64(ctx, space, p):
+    say(f"reduced fp64 {space} p={p}")
+    A = meshgen.affine_parallelepipeds(3, seed=300 + p)
+    out = run(ctx, space, p, A, kind="affine", path="reduced").cpu().numpy()
+    outg = run(ctx, space, p, A, kind="affine", path="general").cpu().numpy()
+    for e in range(3):
+        R = og.gram(space, p, "affine", A[e])
+        compare64(elem(out, e, space, p), R, f"reduced {space} p={p}")
+        compare64(elem(outg, e, space, p), R, f"general-affine {space} p={p}")
+        compare64(elem(out, e, space, p), elem(outg, e, space, p), "reduced vs general")
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [9, 10, 11])
+def test_high_order_sampled(ctx, space, p):
+    say(f"high order sampled {space} p={p}")
+    X = meshgen.perturbed_hexes(1, seed=1100 + p)
+    out = run(ctx, space, p, X).cpu().numpy()
+    n = shapes.dimension(space, p)
+    rng = np.random.default_rng(p)
+    I = rng.integers(0, n, 3000)
+    J = rng.integers(0, n, 3000)
+    I, J = np.minimum(I, J), np.maximum(I, J)
+    I = np.concatenate([I, np.arange(n)])
+    J = np.concatenate([J, np.arange(n)])
+    ref = og.gram_entries(space, p, "trilinear", X[0], I, J)
+    got = out[og.packed_offset(I, J)]
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= TOL64 * scale
+    # the packed output of one element carries no garbage: every entry finite
+    assert np.isfinite(out).all()
+
+
+def test_bad_element_zeroed_and_flagged(ctx, dpg):
+    say("bad element")
+    X = meshgen.perturbed_hexes(3, seed=5)
+    X[1][[0, 7]] = X[1][[7, 0]]
+    st = torch.full((3,), 99, dtype=torch.int32, device="cuda")
+    for space in SPACES:
+        out = run(ctx, space, 3, X, status=st).cpu().numpy()
+        s = st.cpu().numpy()
+        assert list(s) == [0, dpg.EJACOBIAN, 0]
+        m = dpg.packed_len(space, 3)
+        assert np.all(out[m:2 * m] == 0)
+        compare64(elem(out, 0, space, 3), og.gram(space, 3, "trilinear", X[0]), "neighbour 0")
+        compare64(elem(out, 2, space, 3), og.gram(space, 3, "trilinear", X[2]), "neighbour 2")
+
+
+def test_empty_and_invalid(ctx, dpg):
+    say("empty / invalid")
+    g = torch.zeros((0, 8, 3), dtype=torch.float64, device="cuda")
+    out = ctx.gram("H1", 3, g)
+    assert out.numel() == 0
+    X = torch.from_numpy(meshgen.perturbed_hexes(1)).cuda()
+    with pytest.raises(dpg.DpgError):
+        ctx.gram("H1", 12, X)
+    with pytest.raises(dpg.DpgError):
+        ctx.gram("H1", 3, X, nq=7)
+    with pytest.raises(dpg.DpgError):
+        ctx.gram("H1", 3, X, path="reduced")
+
+
+def test_config2_full_size_sampled(ctx, dpg):
+    """4096 distorted hexes, H1 p=7: the benchmark launch; sampled elements vs oracle."""
+    say("config 2 full size fp64 + fp32")
+    X = meshgen.perturbed_hexes(4096, seed=1712)
+    g = torch.from_numpy(X).cuda()
+    m = dpg.packed_len("H1", 7)
+    out = ctx.gram("H1", 7, g)
+    out32 = ctx.gram("H1", 7, g, prec="fp32")
+    torch.cuda.synchronize()
+    for e in (0, 1, 2047, 4095):
+        R = og.gram("H1", 7, "trilinear", X[e])
+        G = og.unpack_upper(out[e * m:(e + 1) * m].cpu().numpy(), 512)
+        compare64(G, R, f"config2 e={e}")
+        G32 = og.unpack_upper(out32[e * m:(e + 1) * m].cpu().numpy().astype(np.float64), 512)
+        fro = np.linalg.norm(G32 - R) / np.linalg.norm(R)
+        say(f"  config2 fp32 e={e} rel fro {fro:.3e}")
+        assert fro <= FP32_REL
+    # whole-batch property: every diagonal entry positive, every entry finite
+    diag = torch.arange(512, device="cuda")
+    doff = diag * (diag + 1) // 2 + diag
+    D = out.view(4096, m)[:, doff]
+    assert bool(torch.isfinite(out).all()) and bool((D > 0).all())
+
+
+@pytest.mark.parametrize("space", ["HCURL", "HDIV"])
+def test_config3_affine_sampled(ctx, dpg, space):
+    say(f"config 3 {space}")
+    for p, E in ((4, 20000), (6, 2000), (8, 400)):
+        A = meshgen.affine_parallelepipeds(E, seed=1713)
+        g = torch.from_numpy(A).cuda()
+        m = dpg.packed_len(space, p)
+        n = dpg.gram_dim(space, p)
+        red = ctx.gram(space, p, g, kind="affine", path="reduced")
+        gen = ctx.gram(space, p, g, kind="affine", path="general")
+        torch.cuda.synchronize()
+        for e in (0, E - 1):
+            R = og.gram(space, p, "affine", A[e])
+            compare64(og.unpack_upper(red[e * m:(e + 1) * m].cpu().numpy(), n), R, f"reduced {space} p={p}")
+            compare64(og.unpack_upper(gen[e * m:(e + 1) * m].cpu().numpy(), n), R, f"general {space} p={p}")
+        d = (red - gen).abs().max().item() / red.abs().max().item()
+        say(f"  {space} p={p} E={E} reduced vs general max rel {d:.2e}")
+        assert d <= TOL64
+        del red, gen
+        torch.cuda.empty_cache()
+
+
+def test_batched_equals_single(ctx, dpg):
+    say("batched uneven p")
+    space, pr, X = meshgen.mixed_batch(300, p_lo=2, p_hi=9, dp=1, seed=1714)
+    lens = np.array([dpg.packed_len(int(s), int(p)) for s, p in zip(space, pr)])
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    total = int(lens.sum())
+    for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        out = torch.full((total,), float("nan"), dtype=dt, device="cuda")
+        ctx.gram_batched(torch.from_numpy(space).cuda(), torch.from_numpy(pr).cuda(),
+                         torch.from_numpy(X).cuda(), torch.from_numpy(off).cuda(), out, prec=prec)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(out).all())
+        for e in range(0, 300, 7):
+            s, p = int(space[e]), int(pr[e])
+            single = ctx.gram(s, p, torch.from_numpy(X[e:e + 1]).cuda(), prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(out[off[e]:off[e] + lens[e]], single), (e, s, p)
+        for e in (0, 1):
+            s, p = int(space[e]), int(pr[e])
+            name = SPACES[s]
+            n = dpg.gram_dim(s, p)
+            G = og.unpack_upper(out[off[e]:off[e] + lens[e]].cpu().numpy().astype(np.float64), n)
+            R = og.gram(name, p, "trilinear", X[e])
+            if prec == "fp64":
+                compare64(G, R, f"batched {name} p={p}")
