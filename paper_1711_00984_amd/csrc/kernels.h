@@ -36,7 +36,19 @@ struct GeneralArgs {
   const void* ftabR;         // F tables in the output precision (reduced path)
   double w0, w1;
   int32_t* status;           // per element (nullptr: none)
+  int slab_group;            // column slabs per workgroup (0: choose from the batch size)
 };
+
+// Column slabs per workgroup: whole elements when the batch alone fills the GPU
+// (about WG_TARGET workgroups), smaller groups for small batches.
+constexpr int64_t WG_TARGET = 2048;
+inline int slab_group_for(int nslab, int64_t n_items, int requested) {
+  if (requested > 0) return requested < nslab ? requested : nslab;
+  int64_t g = n_items * nslab / WG_TARGET;
+  if (g < 1) g = 1;
+  if (g > nslab) g = nslab;
+  return int(g);
+}
 
 // General (sum-factorised quadrature) path; prec 0 = FP64, 1 = FP32.
 hipError_t launch_general_h1(int p, int prec, const GeneralArgs& a, hipStream_t s);
