@@ -149,6 +149,10 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] workload: {E} x {space} p={p} {a.prec}, output {out.numel() * out.element_size() / 1e9:.2f} GB")
 
+    # autotune the work decomposition on this workload (outside the timed region)
+    slab_group = ctx.autotune(space, p, X, out=out, prec=a.prec, stream=stream)
+    log(f"[bench] autotuned slab group: {slab_group}")
+
     def step():
         ctx.gram(space, p, X, out=out, prec=a.prec, stream=stream)
 
@@ -197,7 +201,7 @@ def main():
         "config": {"workload": "4096 trilinear hexes (unit cube vertices + U(-0.15,0.15) noise, seed 1712), "
                                "H1 test Gram p+dp=7, 8^3 Gauss-Legendre points, general O(p^7) path, packed output",
                    "n_elem": E, "space": space, "p": p, "points_per_dir": 8,
-                   "output_bytes": out_bytes},
+                   "output_bytes": out_bytes, "slab_group": slab_group},
         "roofline": roof, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
@@ -214,6 +218,7 @@ def run_extra(ctx, dpg, stream, E, X, out64):
     res = {}
     m = dpg.packed_len("H1", 7)
     out32 = torch.empty(E * m, dtype=torch.float32, device="cuda")
+    ctx.autotune("H1", 7, X, out=out32, prec="fp32", stream=stream)
     wall, per = time_launches(lambda: ctx.gram("H1", 7, X, out=out32, prec="fp32", stream=stream), 10, 2, stream)
     k = float(np.mean(per))
     fl = dpg.general_flops("H1", 7) * E
@@ -233,6 +238,7 @@ def run_extra(ctx, dpg, stream, E, X, out64):
             o = torch.empty(n_e * mm, dtype=torch.float64, device="cuda")
             row = {"space": space, "p": p, "n_elem": n_e}
             for path in ("reduced", "general"):
+                ctx.autotune(space, p, A, kind="affine", out=o, path=path, stream=stream)
                 w, pr = time_launches(lambda: ctx.gram(space, p, A, kind="affine", out=o, path=path,
                                                        stream=stream), 5, 1, stream)
                 kk = float(np.mean(pr))

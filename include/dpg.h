@@ -115,9 +115,11 @@ void dpg_opts_default(dpg_opts* opts);
  * up to p_max + 1, chi_k and chi'_k at the nodes (2.91)-(2.101), the exact 1D
  * integrals F^{rs} (2.103)-(2.114)) in float64 on the host, with a float32
  * rounding, and make them resident on the current device.  p_max in
- * [1, DPG_P_MAX].  Blocks until the tables are on the device.  The context
- * is immutable afterwards and may be shared by threads and streams; it owns
- * its device memory until dpg_ctx_destroy. */
+ * [1, DPG_P_MAX].  Blocks until the tables are on the device.  The tables are
+ * immutable afterwards; the context (tables, tuning table, batched-dispatch
+ * cache) may be shared by threads and streams, and owns its device memory
+ * until dpg_ctx_destroy, which must not run concurrently with other calls on
+ * the context. */
 int dpg_tables_build(int p_max, void* stream, dpg_ctx** ctx);
 int dpg_ctx_destroy(dpg_ctx* ctx);
 
@@ -135,13 +137,34 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
  * length geom->n_elem; p[e] in [1, ctx p_max]) and its packed matrix starts at
  * out + out_offset[e] (device int64, in elements of the output type; regions
  * must not overlap).  All elements share opts (precision, path, weights).
- * The host reads space/p once (a device-to-host copy on stream) to plan the
- * launch; planning state is cached per context for repeated identical
- * batches (same pointers and sizes), and the launch sequence is replayed
- * from a captured HIP graph on later calls. */
+ * The host reads space/p (a device-to-host copy on stream, synchronised) to
+ * plan the launch: elements are bucketed by (space, p) and each bucket's
+ * kernel is captured as an independent node of one HIP graph, so the buckets
+ * run concurrently.  The instantiated graph is cached in the context (up to 8
+ * plans, least recently used evicted) keyed by every pointer, size, option and
+ * a hash of the space/p contents; an identical later call replays it.  Uses
+ * the default point counts only (nq must be 0). */
 int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
                                const dpg_geometry* geom, const int64_t* out_offset, void* out,
                                const dpg_opts* opts, void* stream);
+
+/* Autotuning of the work decomposition (column slabs per workgroup, the
+ * kernels' tile shape along the packed output).  dpg_autotune times every
+ * candidate on the given elements (writing their Gram matrices to out, like
+ * dpg_gram_integrate), records the fastest for (space, p, precision, path)
+ * at the batch-size class floor(log2(n_elem)) in the context, and returns it
+ * in *slab_group (optional).  Blocking: synchronises stream.  Later
+ * dpg_gram_integrate / _batched calls use the table entry of the nearest size
+ * class (within 2 classes); untuned cases use a size heuristic.  The table is
+ * internally synchronised and may be saved/loaded as JSON (host paths). */
+int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out, const dpg_opts* opts,
+                 void* stream, int* slab_group);
+int dpg_tune_save(const dpg_ctx* ctx, const char* path);
+int dpg_tune_load(dpg_ctx* ctx, const char* path);
+/* Tuned slabs per workgroup for this case, 0 if untuned, -1 on bad arguments. */
+int dpg_tune_lookup(const dpg_ctx* ctx, int space, int p, int prec, int reduced, int64_t n_elem);
+/* Number of cached batched-dispatch plans (captured graphs) in the context. */
+int dpg_batch_plans(const dpg_ctx* ctx);
 
 /* Host-only helpers (no device needed): the tables the library builds. */
 /* zeta[L], w[L], chi[(kmax+1) * L], dchi[(kmax+1) * L] with chi[k * L + l] = chi_k(zeta_l). */

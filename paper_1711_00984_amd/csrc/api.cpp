@@ -1,4 +1,4 @@
-// api.cpp -- the C ABI (include/dpg.h): validation, context, dispatch.
+// api.cpp -- the C ABI (include/dpg.h): validation, context, single-space dispatch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,23 +10,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dpg.h"
-#include "kernels.h"
+#include "ctx.h"
 #include "tables.h"
 #include "terms.h"
 
-struct dpg_ctx {
-  int p_max = 0;
-  int device = 0;
-  double* d_tab64 = nullptr;
-  float* d_tab32 = nullptr;
-  double* d_f64 = nullptr;
-  float* d_f32 = nullptr;
-};
+namespace dpg {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -42,37 +34,26 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(DPG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
+const char* last_error() { return g_err.c_str(); }
 
-hipError_t launch_general(int space, int p, int prec, const dpg::GeneralArgs& a, hipStream_t st) {
+int size_class(int64_t n) {
+  int c = 0;
+  while (n > 1) { n >>= 1; ++c; }
+  return c;
+}
+
+static hipError_t launch_general(int space, int p, int prec, const GeneralArgs& a, hipStream_t st) {
   switch (space) {
-    case DPG_H1: return dpg::launch_general_h1(p, prec, a, st);
-    case DPG_HCURL: return dpg::launch_general_hcurl(p, prec, a, st);
-    case DPG_HDIV: return dpg::launch_general_hdiv(p, prec, a, st);
-    case DPG_L2: return dpg::launch_general_l2(p, prec, a, st);
+    case DPG_H1: return launch_general_h1(p, prec, a, st);
+    case DPG_HCURL: return launch_general_hcurl(p, prec, a, st);
+    case DPG_HDIV: return launch_general_hdiv(p, prec, a, st);
+    case DPG_L2: return launch_general_l2(p, prec, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-// Fill the launch arguments shared by every element of one (space, p).
-int make_args(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
-              const dpg_opts& o, dpg::GeneralArgs& a) {
-  const int L = dpg::npoints(space, p);
-  if (o.nq != 0 && o.nq != L)
-    return fail(DPG_EINVAL, "nq=%d: only the default point count (%d) is built", o.nq, L);
-  a = dpg::GeneralArgs{};
-  a.geom = geom->data;
-  a.geom_kind = geom->kind;
-  a.out = out;
-  a.packed_len = dpg::packed_len(space, p);
-  a.tab64 = ctx->d_tab64 + dpg::table_offset(L);
-  a.tabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + dpg::table_offset(L))
-                              : static_cast<const void*>(a.tab64);
-  a.ftabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_f32) : static_cast<const void*>(ctx->d_f64);
-  a.w0 = o.w0;
-  a.w1 = o.w1;
-  a.status = o.status;
-  return DPG_OK;
+bool use_reduced(const dpg_geometry* geom, const dpg_opts& o) {
+  return o.path == DPG_PATH_REDUCED || (o.path == DPG_PATH_AUTO && geom->kind == DPG_GEOM_AFFINE);
 }
 
 int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const dpg_opts& o) {
@@ -90,11 +71,43 @@ int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const 
   return DPG_OK;
 }
 
-bool use_reduced(const dpg_geometry* geom, const dpg_opts& o) {
-  return o.path == DPG_PATH_REDUCED || (o.path == DPG_PATH_AUTO && geom->kind == DPG_GEOM_AFFINE);
+int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
+                    const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
+                    int slab_group, hipStream_t st) {
+  const int L = npoints(space, p);
+  if (o.nq != 0 && o.nq != L)
+    return fail(DPG_EINVAL, "nq=%d: only the default point count (%d) is built", o.nq, L);
+  GeneralArgs a{};
+  a.geom = geom->data;
+  a.geom_kind = geom->kind;
+  a.out = out;
+  a.packed_len = packed_len(space, p);
+  a.tab64 = ctx->d_tab64 + table_offset(L);
+  a.tabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + table_offset(L))
+                              : static_cast<const void*>(a.tab64);
+  a.ftabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_f32) : static_cast<const void*>(ctx->d_f64);
+  a.w0 = o.w0;
+  a.w1 = o.w1;
+  a.status = o.status;
+  a.elem_ids = elem_ids;
+  a.n_items = n_items;
+  a.out_offset = out_offset;
+  a.slab_group = slab_group;
+  const hipError_t e = use_reduced(geom, o) ? launch_affine(space, p, o.prec, a, st)
+                                            : launch_general(space, p, o.prec, a, st);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return DPG_OK;
 }
 
-}  // namespace
+}  // namespace dpg
+
+dpg_ctx::~dpg_ctx() {
+  dpg::destroy_plans(this);
+  if (d_tab64) (void)hipFree(d_tab64);
+}
+
+using dpg::fail;
+using dpg::hip_fail;
 
 extern "C" {
 
@@ -109,20 +122,20 @@ void dpg_opts_default(dpg_opts* o) {
   o->status = nullptr;
 }
 
-const char* dpg_last_error(void) { return g_err.c_str(); }
+const char* dpg_last_error(void) { return dpg::last_error(); }
 
 int64_t dpg_gram_dim(int space, int p) {
-  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
+  if (!dpg::valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
   return dpg::gram_dim(space, p);
 }
 
 int64_t dpg_gram_packed_len(int space, int p) {
-  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
+  if (!dpg::valid_space(space) || p < 1 || p > DPG_P_MAX) return -1;
   return dpg::packed_len(space, p);
 }
 
 double dpg_general_flops(int space, int p) {
-  if (!valid_space(space) || p < 1 || p > DPG_P_MAX) return -1.0;
+  if (!dpg::valid_space(space) || p < 1 || p > DPG_P_MAX) return -1.0;
   return dpg::general_flops(space, p);
 }
 
@@ -181,7 +194,6 @@ int dpg_tables_build(int p_max, void* stream, dpg_ctx** out) {
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_f32, f32.data(), dpg::FTAB_LEN * sizeof(float), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
-    hipFree(base);
     delete c;
     return hip_fail(e, "table upload");
   }
@@ -191,8 +203,6 @@ int dpg_tables_build(int p_max, void* stream, dpg_ctx** out) {
 
 int dpg_ctx_destroy(dpg_ctx* ctx) {
   if (!ctx) return fail(DPG_ENOTINIT, "null context");
-  if (ctx->d_tab64) hipFree(ctx->d_tab64);
-  ctx->d_tab64 = nullptr;
   delete ctx;
   return DPG_OK;
 }
@@ -201,81 +211,15 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
                        const dpg_opts* opts, void* stream) {
   dpg_opts o;
   if (opts) o = *opts; else dpg_opts_default(&o);
-  int rc = check_common(ctx, geom, out, o);
+  int rc = dpg::check_common(ctx, geom, out, o);
   if (rc) return rc;
-  if (!valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
+  if (!dpg::valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
   if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
   if (geom->n_elem == 0) return DPG_OK;
-  dpg::GeneralArgs a;
-  rc = make_args(ctx, space, p, geom, out, o, a);
-  if (rc) return rc;
-  a.n_items = geom->n_elem;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const hipError_t e = use_reduced(geom, o) ? dpg::launch_affine(space, p, o.prec, a, st)
-                                            : launch_general(space, p, o.prec, a, st);
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  return DPG_OK;
-}
-
-int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
-                               const dpg_geometry* geom, const int64_t* out_offset, void* out,
-                               const dpg_opts* opts, void* stream) {
-  dpg_opts o;
-  if (opts) o = *opts; else dpg_opts_default(&o);
-  int rc = check_common(ctx, geom, out, o);
-  if (rc) return rc;
-  const int64_t n = geom->n_elem;
-  if (n == 0) return DPG_OK;
-  if (!space || !p || !out_offset) return fail(DPG_EINVAL, "space, p and out_offset are required");
-  if (n > int64_t(0x7fffffff)) return fail(DPG_EINVAL, "batch too large (%lld elements)", (long long)n);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<int8_t> hs(n), hp(n);
-  hipError_t e = hipMemcpyAsync(hs.data(), space, n, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), p, n, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "reading space/p");
-  // bucket by (space, p): counting sort, heaviest buckets launched first
-  const int NB = 4 * (DPG_P_MAX + 1);
-  std::vector<int64_t> cnt(NB + 1, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    if (!valid_space(hs[i]) || hp[i] < 1 || hp[i] > ctx->p_max)
-      return fail(DPG_EINVAL, "element %lld: space=%d p=%d invalid", (long long)i, hs[i], hp[i]);
-    cnt[hs[i] * (DPG_P_MAX + 1) + hp[i] + 1]++;
-  }
-  for (int b = 0; b < NB; ++b) cnt[b + 1] += cnt[b];
-  std::vector<int32_t> ids(n);
-  {
-    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t i = 0; i < n; ++i) ids[pos[hs[i] * (DPG_P_MAX + 1) + hp[i]]++] = int32_t(i);
-  }
-  int32_t* d_ids = nullptr;
-  e = hipMallocAsync(reinterpret_cast<void**>(&d_ids), n * sizeof(int32_t), st);
-  if (e != hipSuccess) return fail(DPG_ENOMEM, "hipMallocAsync ids: %s", hipGetErrorString(e));
-  e = hipMemcpyAsync(d_ids, ids.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) { hipFreeAsync(d_ids, st); return hip_fail(e, "upload ids"); }
-  // order buckets by estimated cost per element, descending
-  std::vector<int> order;
-  for (int b = 0; b < NB; ++b)
-    if (cnt[b + 1] > cnt[b]) order.push_back(b);
-  std::sort(order.begin(), order.end(), [](int x, int y) {
-    const int sx = x / (DPG_P_MAX + 1), px = x % (DPG_P_MAX + 1);
-    const int sy = y / (DPG_P_MAX + 1), py = y % (DPG_P_MAX + 1);
-    return dpg::packed_len(sx, px) > dpg::packed_len(sy, py);
-  });
-  for (int b : order) {
-    const int sp = b / (DPG_P_MAX + 1), pp = b % (DPG_P_MAX + 1);
-    dpg::GeneralArgs a;
-    rc = make_args(ctx, sp, pp, geom, out, o, a);
-    if (rc) { hipFreeAsync(d_ids, st); return rc; }
-    a.elem_ids = d_ids + cnt[b];
-    a.n_items = cnt[b + 1] - cnt[b];
-    a.out_offset = out_offset;
-    e = use_reduced(geom, o) ? dpg::launch_affine(sp, pp, o.prec, a, st) : launch_general(sp, pp, o.prec, a, st);
-    if (e != hipSuccess) { hipFreeAsync(d_ids, st); return hip_fail(e, "kernel launch"); }
-  }
-  e = hipFreeAsync(d_ids, st);
-  if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
-  return DPG_OK;
+  const bool red = dpg::use_reduced(geom, o);
+  const int g = dpg::tuned_slab_group(ctx, space, p, o.prec, red, geom->n_elem);
+  return dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, geom->n_elem, nullptr, g,
+                              static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,73 @@
+// ctx.h -- library-internal context state shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/dpg.h"
+#include "kernels.h"
+
+namespace dpg {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+inline bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
+
+// Autotuning key: one (space, order, precision, path) at a batch-size class
+// (floor(log2(n_elem))).  Value: column slabs per workgroup and its time.
+struct TuneKey {
+  int space, p, prec, reduced, size_class;
+  bool operator<(const TuneKey& o) const {
+    if (space != o.space) return space < o.space;
+    if (p != o.p) return p < o.p;
+    if (prec != o.prec) return prec < o.prec;
+    if (reduced != o.reduced) return reduced < o.reduced;
+    return size_class < o.size_class;
+  }
+};
+struct TuneVal {
+  int slab_group;
+  float ms;
+};
+
+struct BatchPlan;   // batch.cpp
+
+int size_class(int64_t n);
+
+}  // namespace dpg
+
+struct dpg_ctx {
+  int p_max = 0;
+  int device = 0;
+  double* d_tab64 = nullptr;
+  float* d_tab32 = nullptr;
+  double* d_f64 = nullptr;
+  float* d_f32 = nullptr;
+  // mutable state (the tables above are immutable after dpg_tables_build)
+  mutable std::mutex mu;                                    // guards tune and plans
+  mutable std::map<dpg::TuneKey, dpg::TuneVal> tune;
+  mutable std::vector<std::shared_ptr<dpg::BatchPlan>> plans;   // most recent last
+  ~dpg_ctx();
+};
+
+namespace dpg {
+
+bool use_reduced(const dpg_geometry* geom, const dpg_opts& o);
+int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const dpg_opts& o);
+
+// Launch the kernels of one (space, p) over n_items elements (elem_ids maps
+// items to elements, nullptr = identity; out_offset nullptr = e * packed_len).
+int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
+                    const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
+                    int slab_group, hipStream_t st);
+
+// Slabs per workgroup from the tuning table (0 = not tuned: kernel heuristic).
+int tuned_slab_group(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n);
+
+void destroy_plans(dpg_ctx* ctx);
+
+}  // namespace dpg

@@ -9,12 +9,15 @@
 // quadrature and no shape-function evaluation remain: the kernel is a pure
 // streaming writer of the packed output.
 //
-// Work decomposition: the same column slabs (b, j3) as the general path.
-// Each wave takes one packed column J at a time; its 64 lanes walk the rows
-// I = 0..J, so every store instruction writes 64 consecutive entries.  The
-// F tables are banded (|i - j| <= 2 unless both indices are <= 3), so most
-// entries are exact zeros: a per-direction band test skips the term sums.
+// Work decomposition: the same column-slab groups as the general path.  Each
+// wave takes one packed column J at a time; its 64 lanes walk the rows I = 0..J,
+// so every store instruction writes 64 consecutive entries.  The F tables are
+// banded (|i - j| <= 2 unless both indices are <= 3), so most entries are exact
+// zeros: whole direction-3 planes outside the band are written as zeros without
+// decoding, and the direction-3 factor of each term is hoisted per plane.
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "kernels.h"
 #include "terms.h"
@@ -35,68 +38,65 @@ template <int S, int P> struct AShape {
   static constexpr int R(int a, int d) { return range1d(S, P, a, d); }
   static constexpr int SH(int a, int d) { return shift1d(S, a, d); }
   static constexpr int OFF(int a) { return comp_off(S, P, a); }
-  static constexpr int NSLAB = [] {
+  static constexpr int slab0(int b) {
     int o = 0;
-    for (int c = 0; c < NC; ++c) o += R(c, 2);
+    for (int c = 0; c < b; ++c) o += R(c, 2);
     return o;
-  }();
+  }
+  static constexpr int NSLAB = slab0(NC);
 };
 
-// sum of the terms of block (A, B) at one entry
+template <int S, int A, int B> struct APlan {
+  static constexpr Plan PL = make_plan(S, A, B);
+};
+
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  [&]<int... I>(std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+  }(std::make_integer_sequence<int, N>{});
+}
+
+// The part of column J = (b; j1, j2, j3) that lies in component A: planes of
+// fixed i3, each R1a R2a consecutive rows.  Planes outside the direction-3 band
+// are zero; inside, rows outside the direction-1/2 bands are zero.
 template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ Real block_entry(const Real* sF, const Real* coef, int i1, int i2, int i3, int j1,
-                                            int j2, int j3) {
+__device__ __forceinline__ void column_block(const Real* sF, const Real* coef, int J, int j1, int j2, int j3,
+                                             Real* __restrict__ col, int lane) {
   using Sh = AShape<S, P>;
-  constexpr Plan PL = make_plan(S, A, B);
-  const int a1 = i1 + Sh::SH(A, 0), a2 = i2 + Sh::SH(A, 1), a3 = i3 + Sh::SH(A, 2);
+  constexpr Plan PL = APlan<S, A, B>::PL;
+  constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1), R3a = Sh::R(A, 2);
+  constexpr int PLANE = R1a * R2a;
   const int b1 = j1 + Sh::SH(B, 0), b2 = j2 + Sh::SH(B, 1), b3 = j3 + Sh::SH(B, 2);
-  if (!(band(a1, b1) && band(a2, b2) && band(a3, b3))) return Real(0);
-  Real v = Real(0);
-#pragma unroll
-  for (int t = 0; t < PL.nt; ++t) {
-    const Term& T = PL.t[t];
-    const Real f1 = sF[((2 * T.r[0] + T.s[0]) * KT + a1) * KT + b1];
-    const Real f2 = sF[((2 * T.r[1] + T.s[1]) * KT + a2) * KT + b2];
-    const Real f3 = sF[((2 * T.r[2] + T.s[2]) * KT + a3) * KT + b3];
-    v += coef[t] * f1 * f2 * f3;
-  }
-  return v;
-}
-
-template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ Real entry_in(const Real* sF, const Real* sC, int I, int j1, int j2, int j3) {
-  using Sh = AShape<S, P>;
-  const int loc = I - Sh::OFF(A);
-  const int i1 = loc % Sh::R(A, 0);
-  const int t = loc / Sh::R(A, 0);
-  const int i2 = t % Sh::R(A, 1), i3 = t / Sh::R(A, 1);
-  return block_entry<S, P, Real, A, B>(sF, sC + A * 10, i1, i2, i3, j1, j2, j3);
-}
-
-template <int S, int P, typename Real, int B>
-__device__ __forceinline__ Real entry(const Real* sF, const Real* sC, int I, int j1, int j2, int j3) {
-  using Sh = AShape<S, P>;
-  if constexpr (B >= 2) {
-    if (I >= Sh::OFF(2)) return entry_in<S, P, Real, 2, B>(sF, sC, I, j1, j2, j3);
-  }
-  if constexpr (B >= 1) {
-    if (I >= Sh::OFF(1)) return entry_in<S, P, Real, 1, B>(sF, sC, I, j1, j2, j3);
-  }
-  return entry_in<S, P, Real, 0, B>(sF, sC, I, j1, j2, j3);
-}
-
-template <int S, int P, typename Real, int B>
-__device__ void write_slab(const Real* sF, const Real* sC, bool bad, int j3, Real* __restrict__ outp) {
-  using Sh = AShape<S, P>;
-  constexpr int R1b = Sh::R(B, 0), R2b = Sh::R(B, 1);
-  constexpr int NCOL = R1b * R2b;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < NCOL; c += NT_AFF / 64) {
-    const int j1 = c % R1b, j2 = c / R1b;
-    const int64_t J = Sh::OFF(B) + c + int64_t(NCOL) * j3;
-    Real* col = outp + J * (J + 1) / 2;
-    for (int I = lane; I <= J; I += 64) {
-      col[I] = bad ? Real(0) : entry<S, P, Real, B>(sF, sC, I, j1, j2, j3);
+  for (int i3 = 0; i3 < R3a; ++i3) {
+    const int I0 = Sh::OFF(A) + PLANE * i3;
+    if (I0 > J) break;
+    const int Iend = (I0 + PLANE - 1 < J) ? I0 + PLANE - 1 : J;   // inclusive
+    const int a3 = i3 + Sh::SH(A, 2);
+    if (!band(a3, b3)) {
+      for (int I = I0 + lane; I <= Iend; I += 64) col[I] = Real(0);
+      continue;
+    }
+    // direction-3 factor of every term, uniform over the plane
+    Real w3[PL.nt];
+    sfor<PL.nt>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      w3[t] = coef[t] * sF[((2 * PL.t[t].r[2] + PL.t[t].s[2]) * KT + a3) * KT + b3];
+    });
+    for (int I = I0 + lane; I <= Iend; I += 64) {
+      const int loc = I - I0;
+      const int i1 = loc % R1a, i2 = loc / R1a;
+      const int a1 = i1 + Sh::SH(A, 0), a2 = i2 + Sh::SH(A, 1);
+      Real v = Real(0);
+      if (band(a1, b1) && band(a2, b2)) {
+        sfor<PL.nt>([&](auto T) {
+          constexpr int t = decltype(T)::value;
+          const Real f1 = sF[((2 * PL.t[t].r[0] + PL.t[t].s[0]) * KT + a1) * KT + b1];
+          const Real f2 = sF[((2 * PL.t[t].r[1] + PL.t[t].s[1]) * KT + a2) * KT + b2];
+          v += w3[t] * f1 * f2;
+        });
+      }
+      col[I] = v;
     }
   }
 }
@@ -105,21 +105,22 @@ template <int S, int P, typename Real>
 __global__ void __launch_bounds__(NT_AFF) k_affine(GeneralArgs ga) {
   using Sh = AShape<S, P>;
   __shared__ Real s_F[FTAB_LEN];
-  __shared__ Real s_C[3 * 10];   // coefficients of the terms of blocks (a, b), b fixed
+  __shared__ Real s_C[3][3][10];   // term coefficients of block (a, b)
   __shared__ int s_bad;
   const int tid = threadIdx.x;
   const int64_t blk = blockIdx.x;
-  const int slab = Sh::NSLAB - 1 - int(blk / ga.n_items);
+  const int G = ga.slab_group;
+  const int ngroups = (Sh::NSLAB + G - 1) / G;
+  const int grp = ngroups - 1 - int(blk / ga.n_items);
   const int64_t item = ga.item_base + blk % ga.n_items;
   const int64_t e = ga.elem_ids ? int64_t(ga.elem_ids[item]) : item;
-  int b = 0, j3 = slab;
-#pragma unroll
-  for (int c = 0; c < Sh::NC - 1; ++c)
-    if (b == c && j3 >= Sh::R(c, 2)) { j3 -= Sh::R(c, 2); b = c + 1; }
+  const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
 
   const Real* fR = static_cast<const Real*>(ga.ftabR);
   for (int i = tid; i < FTAB_LEN; i += NT_AFF) s_F[i] = fR[i];
-  if (tid == 0) {
+  if (tid < 32) {
+    // every one of these threads evaluates the constant metric; thread 3 a + b
+    // writes the coefficients of block (a, b)
     const double* g = ga.geom + e * 12;
     double J[3][3], adj[3][3];
     for (int i = 0; i < 3; ++i)
@@ -135,50 +136,77 @@ __global__ void __launch_bounds__(NT_AFF) k_affine(GeneralArgs ga) {
     adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
     const double idet = 1.0 / det;
-    s_bad = !(det > 0.0);
-    double fv[FLD_COUNT];
-    fv[FLD_DETJ] = det;
-    fv[FLD_IDETJ] = idet;
-    for (int s = 0; s < 6; ++s) {
-      const int a = sym_a(s), bb = sym_b(s);
-      fv[FLD_D11 + s] = (adj[a][0] * adj[bb][0] + adj[a][1] * adj[bb][1] + adj[a][2] * adj[bb][2]) * idet;
-      fv[FLD_C11 + s] = (J[0][a] * J[0][bb] + J[1][a] * J[1][bb] + J[2][a] * J[2][bb]) * idet;
-    }
-    for (int a = 0; a < Sh::NC; ++a) {
-      // terms of block (a, b): same construction as the plan used by block_entry
-      const Plan PL = make_plan(S, a < b ? a : b, a < b ? b : a);
-      for (int t = 0; t < 10; ++t) {
-        double c = 0.0;
-        if (t < PL.nt) {
-          const int f = PL.t[t].field;
-          c = PL.t[t].sign * fv[f] * (field_weight(S, f) ? ga.w1 : ga.w0);
-        }
-        s_C[a * 10 + t] = static_cast<Real>(c);
+    if (tid == 0) s_bad = !(det > 0.0);
+    auto fv = [&](int f) -> double {
+      if (f == FLD_DETJ) return det;
+      if (f == FLD_IDETJ) return idet;
+      if (fld_is_D(f)) {
+        const int s = f - FLD_D11, a = sym_a(s), bb = sym_b(s);
+        return (adj[a][0] * adj[bb][0] + adj[a][1] * adj[bb][1] + adj[a][2] * adj[bb][2]) * idet;
       }
-    }
+      const int s = f - FLD_C11, a = sym_a(s), bb = sym_b(s);
+      return (J[0][a] * J[0][bb] + J[1][a] * J[1][bb] + J[2][a] * J[2][bb]) * idet;
+    };
+    sfor<Sh::NC>([&](auto AA) {
+      constexpr int a = decltype(AA)::value;
+      sfor<Sh::NC>([&](auto BB) {
+        constexpr int bb = decltype(BB)::value;
+        if constexpr (a <= bb) {
+          if (tid == 3 * a + bb) {
+            constexpr Plan PL = APlan<S, a, bb>::PL;
+            sfor<10>([&](auto T) {
+              constexpr int t = decltype(T)::value;
+              double c = 0.0;
+              if constexpr (t < PL.nt)
+                c = PL.t[t].sign * fv(PL.t[t].field) * (field_weight(S, PL.t[t].field) ? ga.w1 : ga.w0);
+              s_C[a][bb][t] = static_cast<Real>(c);
+            });
+          }
+        }
+      });
+    });
   }
   __syncthreads();
   Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
   const bool bad = s_bad != 0;
-  if constexpr (Sh::NC == 1) {
-    write_slab<S, P, Real, 0>(s_F, s_C, bad, j3, outp);
-  } else {
-    if (b == 0) write_slab<S, P, Real, 0>(s_F, s_C, bad, j3, outp);
-    else if (b == 1) write_slab<S, P, Real, 1>(s_F, s_C, bad, j3, outp);
-    else write_slab<S, P, Real, 2>(s_F, s_C, bad, j3, outp);
-  }
-  if (ga.status && tid == 0 && (bad || slab == 0)) ga.status[e] = bad ? -4 : 0;
+  const int lane = tid & 63, wave = tid >> 6;
+
+  // columns of the slab group, component by component
+  sfor<Sh::NC>([&](auto BB) {
+    constexpr int b = decltype(BB)::value;
+    constexpr int R1b = Sh::R(b, 0), R2b = Sh::R(b, 1);
+    constexpr int NCOL = R1b * R2b;
+    const int lo = (s_lo > Sh::slab0(b) ? s_lo : Sh::slab0(b)) - Sh::slab0(b);
+    const int hi = (s_hi < Sh::slab0(b) + Sh::R(b, 2) ? s_hi : Sh::slab0(b) + Sh::R(b, 2)) - Sh::slab0(b);
+    for (int c = lo * NCOL + wave; c < hi * NCOL; c += NT_AFF / 64) {
+      const int j3 = c / NCOL, r = c % NCOL;
+      const int j1 = r % R1b, j2 = r / R1b;
+      const int J = Sh::OFF(b) + c;
+      Real* col = outp + int64_t(J) * (J + 1) / 2;
+      if (bad) {
+        for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+        continue;
+      }
+      sfor<b + 1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        column_block<S, P, Real, a, b>(s_F, &s_C[a][b][0], J, j1, j2, j3, col, lane);
+      });
+    }
+  });
+  if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
 }
 
 template <int S, int P, typename Real>
 hipError_t launch_affine_one(const GeneralArgs& a, hipStream_t st) {
   constexpr int NS = AShape<S, P>::NSLAB;
-  const int64_t max_items = int64_t(0x7fffffff) / NS;
   GeneralArgs c = a;
+  c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
+  const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
+  const int64_t max_items = int64_t(0x7fffffff) / ngroups;
   for (int64_t base = 0; base < a.n_items; base += max_items) {
     c.item_base = a.item_base + base;
     c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
-    hipLaunchKernelGGL((k_affine<S, P, Real>), dim3(unsigned(c.n_items * NS)), dim3(NT_AFF), 0, st, c);
+    hipLaunchKernelGGL((k_affine<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_AFF), 0, st, c);
   }
   return hipGetLastError();
 }

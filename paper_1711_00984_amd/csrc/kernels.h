@@ -59,7 +59,4 @@ hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t 
 // Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
 hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);
 
-// Number of work slabs per element (column slabs of the packed output).
-int general_slabs(int space, int p);
-
 }  // namespace dpg

@@ -62,6 +62,17 @@ _lib.dpg_gram_integrate.restype = _i
 _lib.dpg_gram_integrate_batched.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
                                             ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate_batched.restype = _i
+_lib.dpg_autotune.argtypes = [_vp, _i, _i, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp,
+                              ctypes.POINTER(ctypes.c_int)]
+_lib.dpg_autotune.restype = _i
+_lib.dpg_tune_save.argtypes = [_vp, ctypes.c_char_p]
+_lib.dpg_tune_save.restype = _i
+_lib.dpg_tune_load.argtypes = [_vp, ctypes.c_char_p]
+_lib.dpg_tune_load.restype = _i
+_lib.dpg_tune_lookup.argtypes = [_vp, _i, _i, _i, _i, _i64]
+_lib.dpg_tune_lookup.restype = _i
+_lib.dpg_batch_plans.argtypes = [_vp]
+_lib.dpg_batch_plans.restype = _i
 _lib.dpg_host_tables.argtypes = [_i, _i, _vp, _vp, _vp, _vp]
 _lib.dpg_host_tables.restype = _i
 _lib.dpg_host_ftable.argtypes = [_i, _i, _i, _vp]
@@ -194,6 +205,34 @@ class Context:
         _check(_lib.dpg_gram_integrate(self._h, space_id(space), p, ctypes.byref(g), out.data_ptr(),
                                        ctypes.byref(o), _stream_ptr(stream)))
         return out
+
+    def autotune(self, space, p, geom, kind="trilinear", out=None, prec="fp64", path="auto", w0=1.0, w1=1.0,
+                 stream=None):
+        """Time the work decompositions on these elements (dpg_autotune); returns the chosen
+        slabs per workgroup.  Blocking."""
+        g = _geometry(geom, kind)
+        dt = torch.float64 if prec in ("fp64", FP64) else torch.float32
+        n = g.n_elem * packed_len(space, p)
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=geom.device)
+        o = _opts(prec, path, 0, w0, w1, None)
+        best = ctypes.c_int(0)
+        _check(_lib.dpg_autotune(self._h, space_id(space), p, ctypes.byref(g), out.data_ptr(), ctypes.byref(o),
+                                 _stream_ptr(stream), ctypes.byref(best)))
+        return best.value
+
+    def tune_save(self, path):
+        _check(_lib.dpg_tune_save(self._h, str(path).encode()))
+
+    def tune_load(self, path):
+        _check(_lib.dpg_tune_load(self._h, str(path).encode()))
+
+    def tune_lookup(self, space, p, prec="fp64", reduced=False, n_elem=1):
+        return int(_lib.dpg_tune_lookup(self._h, space_id(space), p, 0 if prec in ("fp64", FP64) else 1,
+                                        int(reduced), n_elem))
+
+    def batch_plans(self):
+        return int(_lib.dpg_batch_plans(self._h))
 
     def gram_batched(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
                      w0=1.0, w1=1.0, status=None, stream=None):

@@ -254,3 +254,68 @@ def test_batched_equals_single(ctx, dpg):
             R = og.gram(name, p, "trilinear", X[e])
             if prec == "fp64":
                 compare64(G, R, f"batched {name} p={p}")
+
+
+def test_slab_groups_bitwise_identical_and_autotune(ctx, dpg, tmp_path):
+    """Every work decomposition computes each entry with the same operation
+    sequence, so outputs are bitwise equal; the tuner's choice is one of them."""
+    say("autotune / slab groups")
+    X = torch.from_numpy(meshgen.perturbed_hexes(64, seed=3)).cuda()
+    for space, p in (("H1", 5), ("HCURL", 3), ("HDIV", 4), ("L2", 5)):
+        ref = ctx.gram(space, p, X)
+        torch.cuda.synchronize()
+        best = ctx.autotune(space, p, X)
+        ns = sum(shapes.ranges(space, p)[a][2] for a in range(len(shapes.ranges(space, p))))
+        assert 1 <= best <= ns
+        assert ctx.tune_lookup(space, p, n_elem=64) == best
+        out = ctx.gram(space, p, X)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), space
+    f = tmp_path / "tune.json"
+    ctx.tune_save(f)
+    c2 = dpg.Context(p_max=11)
+    try:
+        assert c2.tune_lookup("H1", 5, n_elem=64) == 0
+        c2.tune_load(f)
+        assert c2.tune_lookup("H1", 5, n_elem=64) == ctx.tune_lookup("H1", 5, n_elem=64)
+        assert c2.tune_lookup("H1", 5, n_elem=64 * 4) == ctx.tune_lookup("H1", 5, n_elem=64)   # nearby class
+        assert c2.tune_lookup("H1", 5, n_elem=64 * 1024) == 0                                 # too far
+    finally:
+        c2.close()
+
+
+def test_batched_graph_replays(ctx, dpg):
+    """The batched dispatch replays a captured graph: repeat it with eager work and
+    synchronisations in between and check every replay against eager single calls."""
+    say("batched graph replay")
+    space, pr, X = meshgen.mixed_batch(120, p_lo=1, p_hi=6, dp=1, seed=99)
+    lens = np.array([dpg.packed_len(int(s), int(p)) for s, p in zip(space, pr)])
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    sp_d, pr_d = torch.from_numpy(space).cuda(), torch.from_numpy(pr).cuda()
+    X_d, off_d = torch.from_numpy(X).cuda(), torch.from_numpy(off).cuda()
+    out = torch.empty(int(lens.sum()), dtype=torch.float64, device="cuda")
+    eager = torch.empty_like(out)
+    for e in range(120):
+        eager[off[e]:off[e] + lens[e]] = ctx.gram(int(space[e]), int(pr[e]), X_d[e:e + 1])
+    torch.cuda.synchronize()
+    n0 = ctx.batch_plans()
+    for rep in range(4):
+        out.fill_(float("nan"))                      # eager work between replays
+        torch.cuda.synchronize()
+        ctx.gram_batched(sp_d, pr_d, X_d, off_d, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+    assert ctx.batch_plans() == n0 + 1               # one plan, replayed
+    pr2 = pr.copy()
+    pr2[0] = 1 if pr2[0] != 1 else 2                 # same pointers, new contents -> new plan
+    pr_d.copy_(torch.from_numpy(pr2))
+    lens2 = np.array([dpg.packed_len(int(s), int(p)) for s, p in zip(space, pr2)])
+    off2 = np.concatenate([[0], np.cumsum(lens2)[:-1]]).astype(np.int64)
+    off_d.copy_(torch.from_numpy(off2))
+    out2 = torch.empty(int(lens2.sum()), dtype=torch.float64, device="cuda")
+    ctx.gram_batched(sp_d, pr_d, X_d, off_d, out2)
+    torch.cuda.synchronize()
+    assert ctx.batch_plans() == n0 + 2
+    single = ctx.gram(int(space[0]), int(pr2[0]), X_d[0:1])
+    torch.cuda.synchronize()
+    assert torch.equal(out2[:lens2[0]], single)
