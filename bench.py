@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-extra", dest="extra", action="store_false")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the replayed serving trace (0: skip the serving measurement)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 4 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -187,6 +189,11 @@ def main():
         extra = run_extra(ctx, dpg, stream, E, X, out)
     del out
     torch.cuda.empty_cache()
+    if a.extra:
+        extra["batched_mixed_50000"] = run_mixed_full(ctx, dpg, stream)
+    serving = None
+    if a.serve_seconds > 0:
+        serving = run_serving(ctx, dpg, a.serve_seconds)
 
     cpu = None
     if not a.no_cpu:
@@ -202,7 +209,7 @@ def main():
                                "H1 test Gram p+dp=7, 8^3 Gauss-Legendre points, general O(p^7) path, packed output",
                    "n_elem": E, "space": space, "p": p, "points_per_dir": 8,
                    "output_bytes": out_bytes, "slab_group": slab_group},
-        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+        "roofline": roof, "cpu_baseline": cpu, "serving": serving, "extra": extra,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -267,6 +274,163 @@ def run_extra(ctx, dpg, stream, E, X, out64):
     del ob
     torch.cuda.empty_cache()
     return res
+
+
+def run_mixed_full(ctx, dpg, stream, n_elem=50000, chunk_bytes=48 << 30):
+    """The uneven-order batch at full size: 50,000 trilinear hexes, space
+    uniform over the four, p uniform in 2..9 plus dp = 1 (seed 1714).  Its FP64
+    output (~0.3 TB) exceeds device memory, so it runs as consecutive element
+    chunks of at most chunk_bytes output, each one batched call into one
+    reused buffer; the rate covers every chunk (planning included)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    sp, pr_, G = meshgen.mixed_batch(n_elem, p_lo=2, p_hi=9, dp=1, seed=1714)
+    lens = np.array([dpg.packed_len(int(s), int(q)) for s, q in zip(sp, pr_)], dtype=np.int64)
+    res = {"n_elem": n_elem, "output_gb_fp64": round(float(lens.sum()) * 8 / 1e9, 1)}
+    for prec, es in (("fp64", 8), ("fp32", 4)):
+        cuts, acc, start = [], 0, 0
+        for e in range(n_elem):
+            if acc + lens[e] * es > chunk_bytes and e > start:
+                cuts.append((start, e))
+                start, acc = e, 0
+            acc += lens[e] * es
+        cuts.append((start, n_elem))
+        chunks = []
+        for a0, a1 in cuts:
+            off = np.concatenate([[0], np.cumsum(lens[a0:a1])[:-1]]).astype(np.int64)
+            chunks.append((torch.from_numpy(sp[a0:a1].copy()).cuda(), torch.from_numpy(pr_[a0:a1].copy()).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(G[a0:a1])).cuda(), torch.from_numpy(off).cuda(),
+                           int(lens[a0:a1].sum())))
+        buf = torch.empty(max(c[4] for c in chunks), dtype=torch.float64 if es == 8 else torch.float32,
+                          device="cuda")
+
+        def one_pass():
+            for s_, p_, g_, o_, _ in chunks:
+                ctx.gram_batched(s_, p_, g_, o_, buf, prec=prec, stream=stream)
+
+        one_pass()                      # plans (graph capture) and warm-up
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            one_pass()
+        torch.cuda.synchronize()
+        w = (time.perf_counter() - t0) / reps
+        res[prec] = {"elements_per_s": round(n_elem / w, 1), "s_per_pass": round(w, 4), "chunks": len(chunks),
+                     "hbm_gbs": round(float(lens.sum()) * es / w / 1e9, 1)}
+        log(f"[bench] mixed 50000 {prec}: {res[prec]}")
+        del buf, chunks
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_serving(ctx, dpg, seconds, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30):
+    """Replay a Poisson serving trace through the serving loop (dpg_serve_*).
+
+    Requests: 64..2048 trilinear hexes, space uniform, p uniform in 2..10 plus
+    dp = 1, FP64, arriving at rate_hz for `seconds`.  The client submits each
+    request at its arrival time, split into element chunks of at most
+    chunk_bytes output (the server admits whole requests only, and a 2048-element
+    H(curl) p=11 request alone is 185 GB), polls, and releases each result as
+    soon as it is complete.  Request latency = arrival -> last chunk pollable
+    (server clock); the server's own statistics are per chunk."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    trace = meshgen.serving_trace(duration_s=seconds, rate_hz=rate_hz, n_lo=64, n_hi=2048, p_lo=2, p_hi=10,
+                                  dp=1, seed=seed)
+    geo = [meshgen.perturbed_hexes(r["n_elem"], seed=r["seed"]).reshape(-1) for r in trace]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(192 << 30, free - (24 << 30)))
+    srv = dpg.Server(ctx, mem_budget_bytes=budget, max_slots=1 << 21, max_inflight=256, max_queue=1 << 16,
+                     n_streams=4, max_merge=32)
+    # warm-up: every (space, order) once, so code-object loading is not in the trace
+    warm = [srv.submit(s, q, meshgen.perturbed_hexes(64, seed=1).reshape(-1), dp=1)
+            for s in range(4) for q in range(2, 11)]
+    pend = set(warm)
+    while pend:
+        for t in list(pend):
+            if srv.poll(t) is not None:
+                srv.release(t)
+                pend.discard(t)
+    srv.reset_stats()
+
+    offered = 0.0
+    backlog = collections.deque()           # (request index, chunk geometry) not yet accepted
+    owner, left, t_done = {}, {}, {}
+    arrival_srv, first, lag = {}, {}, {}
+    i = 0
+    t0 = time.perf_counter()
+    while i < len(trace) or backlog or owner:
+        now = time.perf_counter() - t0
+        while i < len(trace) and trace[i]["t"] <= now:
+            r = trace[i]
+            b1 = dpg.packed_len(r["space"], r["p"] + r["dp"]) * 8
+            per = max(1, chunk_bytes // b1)
+            n = r["n_elem"]
+            offered += n * b1
+            ch = [(i, geo[i][24 * a:24 * min(n, a + per)]) for a in range(0, n, per)]
+            left[i] = len(ch)
+            backlog.extend(ch)
+            i += 1
+        while backlog:
+            ri, g = backlog[0]
+            r = trace[ri]
+            try:
+                t = srv.submit(r["space"], r["p"], g, dp=r["dp"])
+            except dpg.DpgError as e:
+                if e.code == dpg.EAGAIN:
+                    break
+                raise
+            backlog.popleft()
+            owner[t] = ri
+            if ri not in first:
+                # how late the client submitted the request's first chunk
+                first[ri] = t
+                lag[ri] = (time.perf_counter() - t0) - r["t"]
+        for t in list(owner):
+            res = srv.poll(t)
+            if res is None:
+                continue
+            ri = owner.pop(t)
+            assert res["status"] == dpg.OK
+            if first[ri] == t:
+                # arrival on the server clock: first chunk's t_submit minus the client's lag
+                arrival_srv[ri] = res["t_submit"] - lag[ri]
+            t_done[ri] = max(t_done.get(ri, 0.0), res["t_done"])
+            left[ri] -= 1
+            srv.release(t)
+        if not backlog and i < len(trace):
+            time.sleep(max(0.0, min(5e-4, trace[i]["t"] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    assert not any(left.values())
+    st = srv.stats()
+    lat = np.array([t_done[k] - arrival_srv[k] for k in range(len(trace))])
+    elems = sum(r["n_elem"] for r in trace)
+    span = max(t_done.values()) - min(arrival_srv.values())
+    out = {
+        "requests": len(trace), "rate_hz": rate_hz, "duration_s": seconds, "elements": elems,
+        "elements_per_s": round(elems / span, 1), "output_tb_per_s": round(st["bytes"] / span / 1e12, 3),
+        "offered_tb_per_s": round(offered / seconds / 1e12, 3),
+        "latency_p50_ms": round(1e3 * float(np.percentile(lat, 50, method="inverted_cdf")), 3),
+        "latency_p99_ms": round(1e3 * float(np.percentile(lat, 99, method="inverted_cdf")), 3),
+        "latency_max_ms": round(1e3 * float(lat.max()), 3),
+        "chunk_latency_p50_ms": round(1e3 * st["lat_p50"], 3), "chunk_latency_p99_ms": round(1e3 * st["lat_p99"], 3),
+        "chunk_wait_p99_ms": round(1e3 * st["wait_p99"], 3),
+        "chunks": st["completed"], "launches": st["launches"], "max_concurrent_launches": st["max_concurrent_launches"],
+        "budget_gb": round(budget / 1e9, 1), "peak_admitted_gb": round(st["peak_admitted_bytes"] / 1e9, 1),
+        "client_submit_lag_p99_ms": round(1e3 * float(np.percentile(list(lag.values()), 99)), 3),
+        "wall_s": round(wall, 2),
+        "precision": "fp64", "chunk_gb": round(chunk_bytes / 1e9, 1),
+    }
+    log(f"[bench] serving: {out}")
+    srv.close()
+    return out
 
 
 if __name__ == "__main__":

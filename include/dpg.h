@@ -166,6 +166,110 @@ int dpg_tune_lookup(const dpg_ctx* ctx, int space, int p, int prec, int reduced,
 /* Number of cached batched-dispatch plans (captured graphs) in the context. */
 int dpg_batch_plans(const dpg_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Serving loop.  An hp-adaptive driver sends integration requests (one space,
+ * order p + dp, and a batch of elements) as it refines; the server integrates
+ * them on the device with the context's resident tables and keeps each result
+ * in device memory until the client releases it.
+ *
+ *   submit   copies the request's geometry (host or device memory) into
+ *            device-resident element slots and queues the request; returns at
+ *            once with a ticket (DPG_EAGAIN if the queue or the slots are full).
+ *   admit    a scheduler thread admits queued requests in submit order while
+ *            their output fits in the memory budget and fewer than max_inflight
+ *            requests are unfinished (admission by output-matrix bytes).
+ *   launch   requests admitted together that share (space, order, precision,
+ *            path, geometry kind, weights) become one launch (up to max_merge
+ *            requests); launches go out on n_streams streams, so newly admitted
+ *            work overlaps with the work already on the device (continuous
+ *            batching: nothing waits for a batch boundary).
+ *   poll     DPG_PENDING until the request's work has finished, then DPG_OK
+ *            with the result (device pointers and timestamps), or the error
+ *            that failed it.
+ *   release  returns the result's memory (and its slots) to admission.
+ *
+ * The server owns each request's geometry copy from submit, and its output
+ * from admission, until release.  Element e of a result is at
+ * out + e * packed_len (packed 'U' layout as above).  A request whose output
+ * exceeds the budget, or whose elements exceed the slots, is rejected at
+ * submit (DPG_EINVAL): the client splits it into element chunks.  All calls
+ * are thread-safe (many submitters; one internal scheduler thread).
+ * Timestamps are seconds since dpg_serve_create on a monotonic clock; latency
+ * = t_done - t_submit (t_done is when the result became pollable). */
+typedef struct {
+  int64_t mem_budget_bytes; /* output arena (device memory reserved at create)     */
+  int64_t max_slots;        /* element slots for submitted, unreleased requests    */
+  int32_t max_inflight;     /* admitted, unfinished requests                      */
+  int32_t max_queue;        /* submitted, not yet admitted requests               */
+  int32_t n_streams;        /* device streams for launches, 1..8                  */
+  int32_t max_merge;        /* requests per launch, 1..32                         */
+  /* Test hooks (host-side tests of the scheduler).  test_executor = 1 replaces
+   * the device by a timing stub that computes nothing (results have out = NULL;
+   * ctx may be NULL): a launch "finishes" test_launch_s + bytes /
+   * test_bytes_per_s after it starts.  test_fail_launch = k > 0 makes the k-th
+   * launch fail on the host without running: its requests end with DPG_EHIP. */
+  int32_t test_executor;
+  int32_t test_fail_launch;
+  double test_bytes_per_s;
+  double test_launch_s;
+} dpg_serve_cfg;
+
+typedef struct {
+  int32_t space;
+  int32_t p;               /* trial order; the Gram order is p + dp (<= ctx p_max) */
+  int32_t dp;
+  int32_t prec;            /* DPG_FP64 / DPG_FP32                                  */
+  int32_t path;            /* DPG_PATH_*                                           */
+  int32_t geom_on_host;    /* 1: geom.data is host memory, 0: device memory        */
+  dpg_geometry geom;       /* copied at submit; the caller may reuse it at once    */
+  double w0, w1;           /* weights of the value / derivative parts              */
+} dpg_request;
+
+typedef struct {
+  int32_t status;          /* DPG_OK, or the error that failed the request          */
+  int32_t space, p, prec;  /* p = Gram order                                        */
+  int64_t n_elem;
+  int64_t packed_len;      /* entries per element                                   */
+  void* out;               /* device, n_elem * packed_len entries (NULL: stub)      */
+  int32_t* elem_status;    /* device int32[n_elem]: DPG_OK / DPG_EJACOBIAN          */
+  double t_submit, t_admit, t_done;
+} dpg_result;
+
+typedef struct {
+  int64_t submitted, rejected, admitted, completed, failed, launches;
+  int64_t cancelled;                      /* released while still queued            */
+  int64_t queued, inflight;               /* now                                   */
+  int64_t elements;                       /* elements in completed requests         */
+  int64_t budget_bytes, admitted_bytes, peak_admitted_bytes;
+  int64_t max_concurrent_launches;        /* most launches on the device at once    */
+  double bytes;                           /* output bytes of completed requests     */
+  double t_first_submit, t_last_done;
+  double lat_p50, lat_p99, lat_mean, lat_max;   /* submit -> pollable, seconds      */
+  double wait_p50, wait_p99;                    /* submit -> admit, seconds         */
+} dpg_serve_stats;
+
+void dpg_serve_cfg_default(dpg_serve_cfg* cfg);  /* 1 GiB, 2^18 slots, 64, 4096, 4 streams, 32 */
+int dpg_serve_create(dpg_ctx* ctx, const dpg_serve_cfg* cfg, dpg_server** srv);
+int dpg_serve_submit(dpg_server* srv, const dpg_request* req, uint64_t* ticket);
+int dpg_serve_poll(dpg_server* srv, uint64_t ticket, dpg_result* res);
+/* Copy elements [first, first + count) of a finished result to dst (host or
+ * device), asynchronously on stream.  Release the request only after the copy
+ * has completed (synchronise stream first): release hands the memory to the
+ * next admitted request. */
+int dpg_serve_read(dpg_server* srv, uint64_t ticket, void* dst, int64_t first, int64_t count, void* stream);
+/* Copy the status words (int32, DPG_OK / DPG_EJACOBIAN) of elements
+ * [first, first + count) of a finished result to dst (host or device). */
+int dpg_serve_read_status(dpg_server* srv, uint64_t ticket, int32_t* dst, int64_t first, int64_t count,
+                          void* stream);
+/* Release a finished result, or cancel a request that is still queued;
+ * DPG_EAGAIN for a request whose work is on the device. */
+int dpg_serve_release(dpg_server* srv, uint64_t ticket);
+int dpg_serve_stats_get(dpg_server* srv, dpg_serve_stats* st);
+int dpg_serve_stats_reset(dpg_server* srv);   /* clears counters and latency samples */
+/* Stops the scheduler after the device work already started has finished,
+ * and frees all server memory (unreleased results included). */
+int dpg_serve_destroy(dpg_server* srv);
+
 /* Host-only helpers (no device needed): the tables the library builds. */
 /* zeta[L], w[L], chi[(kmax+1) * L], dchi[(kmax+1) * L] with chi[k * L + l] = chi_k(zeta_l). */
 int dpg_host_tables(int L, int kmax, double* zeta, double* w, double* chi, double* dchi);

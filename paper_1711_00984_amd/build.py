@@ -1,6 +1,7 @@
 """Build libdpg.so (HIP kernels for gfx950 + the C ABI) in the package directory.
 
     python -m paper_1711_00984_amd.build        # or: python paper_1711_00984_amd/build.py
+    python -m paper_1711_00984_amd.build --incremental   # reuse up-to-date objects
 
 Objects go to <repo>/_build/; the shared library to
 paper_1711_00984_amd/libdpg.so, where the Python binding loads it.
@@ -32,8 +33,16 @@ def sources():
     return out
 
 
-def _compile(src):
+def _headers_mtime():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs.append(os.path.join(ROOT, "include", "dpg.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, incremental=False, hdr_mtime=0.0):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), hdr_mtime):
+        return obj, 0.0, ""
     cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
@@ -46,15 +55,18 @@ def _compile(src):
     return obj, time.time() - t0, msgs
 
 
-def build(verbose=True, jobs=None):
+def build(verbose=True, jobs=None, incremental=False):
+    """Compile every source (incremental=True skips objects newer than their
+    source and every header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    hdr = _headers_mtime()
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, dt, msgs in ex.map(_compile, srcs):
+        for obj, dt, msgs in ex.map(lambda f: _compile(f, incremental, hdr), srcs):
             objs.append(obj)
-            if verbose:
+            if verbose and dt > 0:
                 print(f"  compiled {os.path.basename(obj)} in {dt:.1f}s", flush=True)
                 if msgs.strip():
                     print(msgs, flush=True)
@@ -70,5 +82,5 @@ def build(verbose=True, jobs=None):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

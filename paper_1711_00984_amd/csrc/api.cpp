@@ -16,25 +16,9 @@
 
 namespace dpg {
 
-namespace {
-thread_local std::string g_err;
-}
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
-
 int hip_fail(hipError_t e, const char* what) {
   return fail(DPG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-const char* last_error() { return g_err.c_str(); }
 
 int size_class(int64_t n) {
   int c = 0;

@@ -9,11 +9,11 @@
 #include <vector>
 
 #include "../../include/dpg.h"
+#include "errors.h"
 #include "kernels.h"
 
 namespace dpg {
 
-int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 inline bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
 

@@ -42,6 +42,33 @@ class Opts(ctypes.Structure):
 
 
 _vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+_i32, _u64 = ctypes.c_int32, ctypes.c_uint64
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", _i64), ("max_slots", _i64), ("max_inflight", _i32), ("max_queue", _i32),
+                ("n_streams", _i32), ("max_merge", _i32), ("test_executor", _i32), ("test_fail_launch", _i32),
+                ("test_bytes_per_s", _d), ("test_launch_s", _d)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("space", _i32), ("p", _i32), ("dp", _i32), ("prec", _i32), ("path", _i32),
+                ("geom_on_host", _i32), ("geom", Geometry), ("w0", _d), ("w1", _d)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", _i32), ("space", _i32), ("p", _i32), ("prec", _i32), ("n_elem", _i64),
+                ("packed_len", _i64), ("out", _vp), ("elem_status", _vp), ("t_submit", _d), ("t_admit", _d),
+                ("t_done", _d)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, _i64) for n in ("submitted", "rejected", "admitted", "completed", "failed", "launches",
+                                     "cancelled", "queued", "inflight", "elements", "budget_bytes", "admitted_bytes",
+                                     "peak_admitted_bytes", "max_concurrent_launches")] + \
+               [(n, _d) for n in ("bytes", "t_first_submit", "t_last_done", "lat_p50", "lat_p99", "lat_mean",
+                                  "lat_max", "wait_p50", "wait_p99")]
+
 
 _lib.dpg_opts_default.argtypes = [ctypes.POINTER(Opts)]
 _lib.dpg_opts_default.restype = None
@@ -73,6 +100,26 @@ _lib.dpg_tune_lookup.argtypes = [_vp, _i, _i, _i, _i, _i64]
 _lib.dpg_tune_lookup.restype = _i
 _lib.dpg_batch_plans.argtypes = [_vp]
 _lib.dpg_batch_plans.restype = _i
+_lib.dpg_serve_cfg_default.argtypes = [ctypes.POINTER(ServeCfg)]
+_lib.dpg_serve_cfg_default.restype = None
+_lib.dpg_serve_create.argtypes = [_vp, ctypes.POINTER(ServeCfg), ctypes.POINTER(_vp)]
+_lib.dpg_serve_create.restype = _i
+_lib.dpg_serve_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
+_lib.dpg_serve_submit.restype = _i
+_lib.dpg_serve_poll.argtypes = [_vp, _u64, ctypes.POINTER(Result)]
+_lib.dpg_serve_poll.restype = _i
+_lib.dpg_serve_read.argtypes = [_vp, _u64, _vp, _i64, _i64, _vp]
+_lib.dpg_serve_read.restype = _i
+_lib.dpg_serve_read_status.argtypes = [_vp, _u64, _vp, _i64, _i64, _vp]
+_lib.dpg_serve_read_status.restype = _i
+_lib.dpg_serve_release.argtypes = [_vp, _u64]
+_lib.dpg_serve_release.restype = _i
+_lib.dpg_serve_stats_get.argtypes = [_vp, ctypes.POINTER(ServeStats)]
+_lib.dpg_serve_stats_get.restype = _i
+_lib.dpg_serve_stats_reset.argtypes = [_vp]
+_lib.dpg_serve_stats_reset.restype = _i
+_lib.dpg_serve_destroy.argtypes = [_vp]
+_lib.dpg_serve_destroy.restype = _i
 _lib.dpg_host_tables.argtypes = [_i, _i, _vp, _vp, _vp, _vp]
 _lib.dpg_host_tables.restype = _i
 _lib.dpg_host_ftable.argtypes = [_i, _i, _i, _vp]
@@ -246,6 +293,113 @@ class Context:
                                                out_offset.data_ptr(), out.data_ptr(), ctypes.byref(o),
                                                _stream_ptr(stream)))
         return out
+
+
+class Server:
+    """Serving loop (dpg_serve_*): submit requests, poll results, release them.
+
+    ctx may be None only with test_executor=True (the scheduler's timing stub,
+    which computes nothing).  Results stay in the server's device memory until
+    release(); read() copies elements of a result into a tensor.
+    """
+
+    def __init__(self, ctx=None, mem_budget_bytes=1 << 30, max_slots=1 << 18, max_inflight=64, max_queue=4096,
+                 n_streams=4, max_merge=32, test_executor=False, test_fail_launch=0, test_bytes_per_s=1e12,
+                 test_launch_s=0.0):
+        c = ServeCfg()
+        _lib.dpg_serve_cfg_default(ctypes.byref(c))
+        c.mem_budget_bytes, c.max_slots = int(mem_budget_bytes), int(max_slots)
+        c.max_inflight, c.max_queue, c.n_streams, c.max_merge = max_inflight, max_queue, n_streams, max_merge
+        c.test_executor, c.test_fail_launch = int(bool(test_executor)), int(test_fail_launch)
+        c.test_bytes_per_s, c.test_launch_s = float(test_bytes_per_s), float(test_launch_s)
+        self._h = ctypes.c_void_p()
+        self._ctx = ctx   # keeps the tables alive while the server runs
+        _check(_lib.dpg_serve_create(ctx.handle if ctx is not None else None, ctypes.byref(c),
+                                     ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.dpg_serve_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, space, p, geom, dp=0, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0):
+        """Queue one request; returns its ticket.  geom: float64 numpy array or
+        tensor (host or device) of n_elem * 24 (trilinear) or * 12 (affine)
+        values, copied before this returns.  Raises DpgError (code EAGAIN when
+        the queue or the element slots are full)."""
+        kind = {"trilinear": TRILINEAR, "affine": AFFINE}.get(kind, kind)
+        per = 24 if kind == TRILINEAR else 12
+        if isinstance(geom, torch.Tensor):
+            if geom.dtype != torch.float64 or not geom.is_contiguous():
+                raise ValueError("geometry must be a contiguous float64 tensor")
+            ptr, numel, on_host = geom.data_ptr(), geom.numel(), int(not geom.is_cuda)
+        else:
+            import numpy as np
+            if not (isinstance(geom, np.ndarray) and geom.dtype == np.float64 and geom.flags.c_contiguous):
+                raise ValueError("geometry must be a C-contiguous float64 array")
+            ptr, numel, on_host = geom.ctypes.data, geom.size, 1
+        if numel % per:
+            raise ValueError(f"geometry size {numel} is not a multiple of {per}")
+        r = Request(space_id(space), int(p), int(dp), {"fp64": FP64, "fp32": FP32}.get(prec, prec),
+                    PATHS.get(path, path), on_host, Geometry(kind, 0, numel // per, ptr), float(w0), float(w1))
+        t = _u64(0)
+        _check(_lib.dpg_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending; else a dict with status, space, p (Gram order), prec,
+        n_elem, packed_len, out / elem_status (device addresses) and the
+        timestamps t_submit, t_admit, t_done (seconds since the server started)."""
+        r = Result()
+        rc = _lib.dpg_serve_poll(self._h, ticket, ctypes.byref(r))
+        if rc == PENDING:
+            return None
+        if rc != OK and r.n_elem == 0:
+            raise DpgError(rc, last_error())
+        return {f: getattr(r, f) for f, _ in Result._fields_}
+
+    def read(self, ticket, first=0, count=None, out=None, stream=None):
+        """Copy elements [first, first+count) of a finished result into out (a
+        device tensor by default), asynchronously on stream."""
+        r = self.poll(ticket)
+        if r is None:
+            raise DpgError(EINVAL, f"request {ticket} has not finished")
+        count = r["n_elem"] - first if count is None else count
+        dt = torch.float64 if r["prec"] == FP64 else torch.float32
+        n = count * r["packed_len"]
+        if out is None:
+            out = torch.empty(n, dtype=dt, device="cuda")
+        elif out.dtype != dt or out.numel() < n or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or size")
+        _check(_lib.dpg_serve_read(self._h, ticket, out.data_ptr(), first, count, _stream_ptr(stream)))
+        return out
+
+    def read_status(self, ticket, first=0, count=None, stream=None):
+        """Status words (int32 device tensor) of elements [first, first+count)."""
+        r = self.poll(ticket)
+        if r is None:
+            raise DpgError(EINVAL, f"request {ticket} has not finished")
+        count = r["n_elem"] - first if count is None else count
+        out = torch.empty(count, dtype=torch.int32, device="cuda")
+        _check(_lib.dpg_serve_read_status(self._h, ticket, out.data_ptr(), first, count, _stream_ptr(stream)))
+        return out
+
+    def release(self, ticket):
+        _check(_lib.dpg_serve_release(self._h, ticket))
+
+    def stats(self):
+        s = ServeStats()
+        _check(_lib.dpg_serve_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServeStats._fields_}
+
+    def reset_stats(self):
+        _check(_lib.dpg_serve_stats_reset(self._h))
 
 
 def exported_symbols():
