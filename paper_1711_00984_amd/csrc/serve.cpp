@@ -6,10 +6,14 @@
 //   element slots  per slot: trilinear geometry (24 doubles), affine geometry
 //                  (12 doubles), status word, output offset
 //   item maps      2 * max_slots int32 (merged launches)
-// A request's geometry stays in its slots, and its output in the arena,
-// from submit / admission until release.
+// plus pinned host staging of 24 doubles per slot.  Host geometry is copied
+// into the staging at submit (no device work on the client's thread) and
+// uploaded on the launch stream just before the request's kernels; device
+// geometry is copied into the slots at submit.  A request's geometry stays in
+// its slots, and its output in the arena, until release.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -56,6 +60,8 @@ class HipExecutor final : public Executor {
     }
     e = hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipHostMalloc(reinterpret_cast<void**>(&stage_), size_t(slots_) * 24 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(DPG_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
     return DPG_OK;
   }
 
@@ -65,20 +71,25 @@ class HipExecutor final : public Executor {
     for (hipEvent_t ev : events_) (void)hipEventDestroy(ev);
     for (hipStream_t s : streams_) (void)hipStreamDestroy(s);
     if (upload_) (void)hipStreamDestroy(upload_);
+    if (stage_) (void)hipHostFree(stage_);
     if (slot_mem_) (void)hipFree(slot_mem_);
     if (out_) (void)hipFree(out_);
   }
 
-  int put_geometry(const dpg_request& rq, int64_t slot0) override {
+  int put_geometry(const dpg_request& rq, int64_t slot0, bool* staged) override {
     const int st = geom_stride(rq.geom.kind);
     if (slot0 < 0 || slot0 + rq.geom.n_elem > slots_) return fail(DPG_EINVAL, "slot range outside the arena");
-    double* dst = (rq.geom.kind == DPG_GEOM_AFFINE ? geo_aff_ : geo_tri_) + slot0 * st;
     const size_t bytes = size_t(rq.geom.n_elem) * st * sizeof(double);
+    if (rq.geom_on_host) {   // slots of this request are exclusive: no copy of them is in flight
+      std::memcpy(stage_ + slot0 * 24, rq.geom.data, bytes);
+      *staged = true;
+      return DPG_OK;
+    }
+    double* dst = (rq.geom.kind == DPG_GEOM_AFFINE ? geo_aff_ : geo_tri_) + slot0 * st;
     std::lock_guard<std::mutex> lk(upload_mu_);
     hipError_t e = hipSetDevice(ctx_->device);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(dst, rq.geom.data, bytes, rq.geom_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                         upload_);
+      e = hipMemcpyAsync(dst, rq.geom.data, bytes, hipMemcpyDeviceToDevice, upload_);
     if (e == hipSuccess) e = hipStreamSynchronize(upload_);
     return e == hipSuccess ? DPG_OK : hip_fail(e, "geometry copy");
   }
@@ -97,6 +108,13 @@ class HipExecutor final : public Executor {
     o.w1 = w0.w1;
     double* geo = w0.kind == DPG_GEOM_AFFINE ? geo_aff_ : geo_tri_;
     const int gs = geom_stride(w0.kind);
+    for (const Work& w : l.work) {   // staged host geometry goes up first, in stream order
+      if (!w.staged) continue;
+      if (w.slot0 < 0 || w.slot0 + w.n > slots_) return fail(DPG_EINVAL, "request outside the arenas");
+      e = hipMemcpyAsync(geo + w.slot0 * gs, stage_ + w.slot0 * 24, size_t(w.n) * gs * sizeof(double),
+                         hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "geometry upload");
+    }
     int rc;
     if (l.work.size() == 1) {
       // one request: its slots and its output range are contiguous
@@ -201,6 +219,7 @@ class HipExecutor final : public Executor {
   int32_t* ids_ = nullptr;
   std::vector<hipStream_t> streams_;
   hipStream_t upload_ = nullptr;
+  double* stage_ = nullptr;   // pinned, 24 doubles per slot
   std::mutex upload_mu_;
   std::vector<hipEvent_t> events_, events_free_;   // events_free_ is used under the server lock
 };

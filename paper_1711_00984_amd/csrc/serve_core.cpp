@@ -161,7 +161,8 @@ int Server::submit(const dpg_request& rq, uint64_t* ticket) {
     r.state = QUEUED;
     reqs_.emplace(t, r);   // not in queue_ yet: invisible to the scheduler until its geometry is on the device
   }
-  const int rc = ex_->put_geometry(rq, r.w.slot0);
+  bool staged = false;
+  const int rc = ex_->put_geometry(rq, r.w.slot0, &staged);
   {
     std::lock_guard<std::mutex> lk(mu_);
     if (rc != DPG_OK) {
@@ -170,6 +171,7 @@ int Server::submit(const dpg_request& rq, uint64_t* ticket) {
       ++st_rejected_;
       return rc;
     }
+    reqs_.at(t).w.staged = staged;
     queue_.push_back(t);
     ++st_submitted_;
     if (st_first_submit_ < 0) st_first_submit_ = t_submit;
@@ -443,7 +445,7 @@ class StubExecutor final : public Executor {
         lat_(c.test_launch_s > 0 ? c.test_launch_s : 0.0),
         busy_(c.n_streams, 0.0),
         t0_(std::chrono::steady_clock::now()) {}
-  int put_geometry(const dpg_request& req, int64_t) override {
+  int put_geometry(const dpg_request& req, int64_t, bool*) override {
     return req.geom.data ? DPG_OK : fail(DPG_EINVAL, "NULL geometry");
   }
   int start(Launch& l) override {

@@ -59,6 +59,7 @@ struct Work {
   int64_t slot0 = 0;       // first element slot (geometry, status)
   int64_t out_off = 0;     // byte offset of the output in the output arena
   int64_t packed_len = 0;
+  bool staged = false;     // geometry waits in host staging; the launch uploads it
 };
 
 // A launch: requests with one key, ids_off = start of its item->slot map.
@@ -73,9 +74,11 @@ struct Launch {
 class Executor {
  public:
   virtual ~Executor() = default;
-  // Copy a request's geometry into its slots (called at submit, without the
-  // server lock).  Blocking until the copy is complete.
-  virtual int put_geometry(const dpg_request& req, int64_t slot0) = 0;
+  // Take a copy of a request's geometry for its slots (called at submit,
+  // without the server lock).  Device geometry is copied into the slots before
+  // this returns; host geometry may instead be staged in host memory
+  // (*staged = true), and start() then uploads it ahead of the kernels.
+  virtual int put_geometry(const dpg_request& req, int64_t slot0, bool* staged) = 0;
   // Enqueue the launch; on success l.handle is set.
   virtual int start(Launch& l) = 0;
   // 1 finished, 0 still running, < 0 error code (the launch failed).
