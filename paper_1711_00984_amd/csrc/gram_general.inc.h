@@ -22,18 +22,29 @@
 // (a == b, i3 == j3) only form i2 <= j2, and i1 <= j1 when i2 == j2: the
 // symmetry used by fillsymmetric.
 //
-// Stages 2 and 1 are GEMMs with element-independent left factors built from
-// the 1D tables:
-//   stage 2: rows (pair, l), columns x = (i2, j2), K = (q, m); NP pairs
-//            (i3, i3+1, ...) are batched so that NP*L fills 16 MFMA rows;
-//   stage 1: rows x, columns y = (i1, j1), K = (g, l).
-// The table factors (MFMA B operands) depend only on the block and on the
-// wave's x- or y-tile, so each wave keeps them in registers for the whole
-// block; only the element data (A_q, B_g) streams through LDS.
+// Pairs (i3, j3) are processed in batches.  Stage 3 of a batch writes A_q for
+// all its pairs to LDS (double-buffered, so stage 3 of the next batch runs
+// while the waves work on this one).  Then each wave takes work items (pair
+// group, x-tile of 16 x = (i2, j2)) and runs stages 2 and 1 for it without
+// touching LDS in between:
+//
+//   stage 2: C2[row][x] = sum_k A[row][k] U2[k][x], rows = (pair, l) of NP
+//            pairs padded to LP = 4 ceil(L/4) points, k = (q, m); one MFMA
+//            accumulator per group g;
+//   stage 1: G[x][y] = sum_k C2^T[x][k] U1[k][y], k = (g, l), y = (i1, j1).
+//
+// The MFMA accumulator layout of gfx950 makes register r of stage 2's
+// accumulator, read by the same lane, exactly the A operand of stage 1 for
+// k = l = 4 rho + (lane / 16) when the stage-2 rows are ordered as below, so
+// the intermediate B_g never leaves the registers.  The table operands U2, U1
+// (products of two 1D table values) come from a per-block LDS table, from
+// registers, or from the 1D tables with immediate offsets (k-slot -> (q, m)
+// and (g, l) are compile-time), whichever the LDS budget allows.
 //
 // MFMA operand layout (v_mfma_*_16x16x4): lane = i + 16 k holds A[i][k] and
-// B[k][j = i].  In stage 1, row i of the A operand carries x = xbase +
-// Mma::arow(i), chosen so that accumulator register r of lane group g holds x
+// B[k][j = i]; accumulator register r of lane (g = lane / 16, j = lane % 16)
+// holds C[crow(g, r)][j].  Stage-1 row i is stage-2 column i, which carries
+// x = xbase + arow(i), chosen so that register r of lane group g holds x
 // offset g + 4 r: four consecutive x = (i2, j2), i.e. consecutive rows I of one
 // packed column, so a store instruction writes runs of 4 R1 values.
 #pragma once
@@ -52,31 +63,44 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 template <typename Real> struct Mma;
 // Accumulator register r of lane (g = lane/16, j = lane%16) holds C[row][j] with
 // row = g + 4 r for the f64 instruction and row = 4 g + r for the f32 one
-// (both checked on gfx950).  arow(i) is the x offset that A-operand row i must
+// (both checked on gfx950).  arow(i) is the x offset that stage-1 row i must
 // carry so that register r of lane group g always holds x offset g + 4 r.
 template <> struct Mma<double> {
   typedef v4d acc;
   static __device__ __forceinline__ acc mac(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int arow(int i) { return i; }
-  static __device__ __forceinline__ int crow(int g, int r) { return g + 4 * r; }
+  static constexpr __host__ __device__ int arow(int i) { return i; }
+  static constexpr __host__ __device__ int crow(int g, int r) { return g + 4 * r; }
 };
 template <> struct Mma<float> {
   typedef v4f acc;
   static __device__ __forceinline__ acc mac(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int arow(int i) { return (i >> 2) + 4 * (i & 3); }
-  static __device__ __forceinline__ int crow(int g, int r) { return 4 * g + r; }
+  static constexpr __host__ __device__ int arow(int i) { return (i >> 2) + 4 * (i & 3); }
+  static constexpr __host__ __device__ int crow(int g, int r) { return 4 * g + r; }
 };
 
 constexpr int NTHREADS = 256;
-constexpr int NC2 = 16;    // stage-2 MFMA rows: NP pairs x L points, padded
+// Register-budget knobs (Reals per thread): metric field column of stage 3,
+// stage-2 table operand of a fixed x-tile, y-tiles per stage-1 accumulator set.
+#ifndef DPG_REGF_MAX
+#define DPG_REGF_MAX 48
+#endif
+#ifndef DPG_C2_MAX
+#define DPG_C2_MAX 24
+#endif
+#ifndef DPG_YB
+#define DPG_YB 4
+#endif
+#ifndef DPG_MINW2_LMAX
+#define DPG_MINW2_LMAX 8
+#endif
 constexpr int ru16(int x) { return (x + 15) / 16 * 16; }
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
-constexpr int pairs_per_batch(int L) { return imin(4, L <= 16 ? imax(1, 16 / L) : 1); }
+constexpr int lpad(int L) { return 4 * ((L + 3) / 4); }   // points padded to whole k-steps
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled at compile time
 template <int N, typename F>
@@ -89,6 +113,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <int S, int P> struct Shape {
   static constexpr int NC = ncomp(S);
   static constexpr int L = npoints(S, P);
+  static constexpr int LP = lpad(L);        // l, m padded to a multiple of 4
+  static constexpr int RPP = LP / 4;        // stage-2 accumulator registers per pair
+  static constexpr int NP = 4 / RPP;        // pairs per stage-2 row tile (16 rows)
   static constexpr int R(int a, int d) { return range1d(S, P, a, d); }
   static constexpr int SH(int a, int d) { return shift1d(S, a, d); }
   static constexpr int OFF(int a) { return comp_off(S, P, a); }
@@ -104,54 +131,26 @@ template <int S, int P> struct Shape {
 template <int S, int P, int A, int B> struct Blk {
   using Sh = Shape<S, P>;
   static constexpr Plan PL = make_plan(S, A, B);
-  static constexpr int L = Sh::L;
-  static constexpr int NP = pairs_per_batch(L);
+  static constexpr int L = Sh::L, LP = Sh::LP, RPP = Sh::RPP, NP = Sh::NP;
   static constexpr int R1a = Sh::R(A, 0), R1b = Sh::R(B, 0), R2a = Sh::R(A, 1), R2b = Sh::R(B, 1);
   static constexpr int R3a = Sh::R(A, 2), R3b = Sh::R(B, 2);
   static constexpr int NY = R1a * R1b, NYT = (NY + 15) / 16;
-  static constexpr int NX = R2a * R2b, NXP = ru16(NX);
-  static constexpr int NXD = R2a * (R2a + 1) / 2, NXDP = ru16(NXD);
+  static constexpr int NX = R2a * R2b, NXT = (NX + 15) / 16;
+  static constexpr int NXD = R2a * (R2a + 1) / 2, NXDT = (NXD + 15) / 16;
   static constexpr int NG = make_plan(S, A, B).ng;
   static constexpr int NQ = make_plan(S, A, B).nq;
-  static constexpr int nqg(int g) {
-    const Plan pl = make_plan(S, A, B);
-    int c = 0;
-    for (int q = 0; q < pl.nq; ++q) c += pl.qg[q] == g;
-    return c;
-  }
-  static constexpr int qpos(int q) {
-    const Plan pl = make_plan(S, A, B);
-    int c = 0;
-    for (int r = 0; r < q; ++r) c += pl.qg[r] == pl.qg[q];
-    return c;
-  }
-  // i-th q slot of group g
-  static constexpr int gq(int g, int i) {
-    const Plan pl = make_plan(S, A, B);
-    for (int q = 0; q < pl.nq; ++q)
-      if (pl.qg[q] == g && qpos(q) == i) return q;
-    return 0;
-  }
-  static constexpr int krow0(int g) {
-    int o = 0;
-    for (int h = 0; h < g; ++h) o += nqg(h) * L;
-    return o;
-  }
-  static constexpr int arow_q(int q) { return krow0(make_plan(S, A, B).qg[q]) + qpos(q) * L; }
-  static constexpr int ks2(int g) { return (nqg(g) * L + 3) / 4; }
-  static constexpr int koff2(int g) {
-    int o = 0;
-    for (int h = 0; h < g; ++h) o += ks2(h);
-    return o;
-  }
-  static constexpr int KS2 = koff2(NG);
-  static constexpr int K1 = NG * L, KS1 = (K1 + 3) / 4;
-  static constexpr int QSPLIT = imax(1, imin(NQ, NTHREADS / (NP * L * L)));
 };
 
-template <int S, int P, typename Real> struct Lds {
+// Per (space, order, precision): LDS layout and batch shape, chosen at
+// compile time for the best estimated efficiency within the LDS budget.
+//   NB     pair groups (stage-2 row tiles) per batch: more work items per
+//          batch balance the four waves when x-tiles do not divide by 4
+//   ABUF   2 = double-buffered stage-3 output (stage 3 of the next batch
+//          overlaps this batch's MFMA work), 1 = single buffer
+//   U1TAB  stage-1 table operand precomputed in LDS per block
+template <int S, int P, typename Real> struct Cfg {
   using Sh = Shape<S, P>;
-  static constexpr int L = Sh::L;
+  static constexpr int L = Sh::L, LP = Sh::LP, RPP = Sh::RPP, NP = Sh::NP;
   template <typename F> static constexpr int over_blocks(F f) {
     int m = 0;
     for (int a = 0; a < Sh::NC; ++a)
@@ -161,28 +160,53 @@ template <int S, int P, typename Real> struct Lds {
   static constexpr int NF = over_blocks([](int a, int b) { return make_plan(S, a, b).nf; });
   static constexpr int NQ = over_blocks([](int a, int b) { return make_plan(S, a, b).nq; });
   static constexpr int NG = over_blocks([](int a, int b) { return make_plan(S, a, b).ng; });
-  static constexpr int NXP = over_blocks([](int a, int b) { return ru16(Sh::R(a, 1) * Sh::R(b, 1)); });
+  static constexpr int NYT = over_blocks([](int a, int b) { return (Sh::R(a, 0) * Sh::R(b, 0) + 15) / 16; });
   static constexpr int FLD_LEN = NF * L * L * L;
-  static constexpr int A_LEN = NQ * L * NC2;
-  static constexpr int T_LEN = 2 * KT * L;
-  static constexpr int BUDGET = 150 * 1024;
-  static constexpr int bytes(int xch) {
-    return int(sizeof(Real)) * (FLD_LEN + A_LEN + T_LEN + NG * NC2 * xch) + 8 * (2 * L + 24) + 256;
+  static constexpr int AONE = NQ * LP * 16;              // stage-3 output of one pair group
+  static constexpr int T_LEN = 2 * KT * L + 8;           // chi, chi' tables (+ tail read by padded k)
+  static constexpr int U1_LEN = NG * RPP * NYT * 64;
+  static constexpr int SMALL = 8 * (2 * L + 24) + 2 * 80 + 64;
+  static constexpr int BUDGET = 160 * 1024;
+  static constexpr int bytes(int nb, int abuf, int u1) {
+    return int(sizeof(Real)) * (FLD_LEN + abuf * nb * AONE + T_LEN + (u1 ? U1_LEN : 0)) + SMALL;
   }
-  // x-chunk width of stages 2/1: as wide as possible within the LDS budget
-  static constexpr int XCH = [] {
-    int x = NXP;
-    while (x > 16 && bytes(x) > BUDGET) x -= 16;
-    return x;
+  // fraction of wave time doing useful work items, over the blocks' non-diagonal batches
+  static constexpr double balance(int nb) {
+    double s = 0;
+    int n = 0;
+    for (int a = 0; a < Sh::NC; ++a)
+      for (int b = a; b < Sh::NC; ++b) {
+        const int items = nb * ((Sh::R(a, 1) * Sh::R(b, 1) + 15) / 16);
+        s += double(items) / (4.0 * ((items + 3) / 4));
+        ++n;
+      }
+    return s / n;
+  }
+  static constexpr int CHOICE = [] {
+    double best = -1;
+    int pick = 0;
+    for (int nb = 1; nb <= 4; nb *= 2)
+      for (int abuf = 2; abuf >= 1; --abuf)
+        for (int u1 = 1; u1 >= 0; --u1) {
+          if (bytes(nb, abuf, u1) > BUDGET) continue;
+          // one workgroup per CU leaves no second workgroup to overlap barriers and stalls
+          const double occ = bytes(nb, abuf, u1) * 2 <= BUDGET ? 1.0 : 0.7;
+          const double sc = balance(nb) * occ * (abuf == 2 ? 1.0 : 0.9) * (u1 ? 1.0 : 0.88) * (nb == 1 ? 1.0 : 0.995);
+          if (sc > best + 1e-9) { best = sc; pick = nb * 100 + abuf * 10 + u1; }
+        }
+    return pick;
   }();
-  static_assert(bytes(XCH) <= BUDGET, "LDS budget exceeded");
-  static constexpr int B_LEN = NG * NC2 * XCH;
+  static_assert(CHOICE > 0, "no LDS layout fits");
+  static constexpr int NB = CHOICE / 100, ABUF = (CHOICE / 10) % 10;
+  static constexpr bool U1TAB = CHOICE % 10;
+  static constexpr int NBP = NB * NP;                    // pairs per batch
+  static constexpr int BYTES = bytes(NB, ABUF, U1TAB);
 };
 
 struct SmemPtrs {
   void* fld;
   void* A;
-  void* B;
+  void* U1;
   void* T;
   double* z;
   double* w;
@@ -190,7 +214,6 @@ struct SmemPtrs {
   unsigned char* xd;
   int* bad;
 };
-
 // ---------------------------------------------------------------------------
 // geometry
 // ---------------------------------------------------------------------------
@@ -252,22 +275,6 @@ __device__ __forceinline__ double field_value(int fid, const double J[3][3], con
   return (J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b]) * idet;
 }
 
-// ---------------------------------------------------------------------------
-// LDS index of B_g(col, x): rows of XS entries, odd rows rotated by 16 when
-// XS is a multiple of 32 so that the four rows touched by one wave-wide
-// access fall into alternating halves of the bank space.
-// ---------------------------------------------------------------------------
-template <int XS>
-__device__ __forceinline__ int bidx(int row, int col, int x) {
-  if constexpr (XS % 32 == 0) {
-    int xr = x + 16 * (col & 1);
-    if (xr >= XS) xr -= XS;
-    return row * XS + xr;
-  } else {
-    return row * XS + x;
-  }
-}
-
 // (i2, j2) of x slot s: all pairs (i2 fastest) or the triangle i2 <= j2
 template <int R2a, bool DIAG>
 __device__ __forceinline__ void decode_x(const unsigned char* xd, int s, int& i2, int& j2) {
@@ -275,53 +282,40 @@ __device__ __forceinline__ void decode_x(const unsigned char* xd, int s, int& i2
   else { i2 = s % R2a; j2 = s / R2a; }
 }
 
-// stage-2 B operand: u = T^<r2>_{i2+sa}(m) T^<s2>_{j2+sb}(m) for the group-local k
-template <int S, int P, typename Real, int A, int B, bool DIAG, int G>
-__device__ __forceinline__ Real u2_value(const Real* sT, const unsigned char* xd, int x, int kk) {
-  using BC = Blk<S, P, A, B>;
-  using Sh = Shape<S, P>;
-  constexpr int L = BC::L, KTL = KT * L;
-  constexpr int NXv = DIAG ? BC::NXD : BC::NX;
-  constexpr int KG = BC::nqg(G) * L;
-  if (x >= NXv || kk >= KG) return Real(0);
-  const int qi = kk / L, m = kk - qi * L;
-  int r2 = 0, s2 = 0;
-  constexpr int NQG = BC::nqg(G);
-  static_for<NQG>([&](auto I) {
-    constexpr int q = BC::gq(G, decltype(I)::value);
-    if (qi == decltype(I)::value) { r2 = BC::PL.qr2[q]; s2 = BC::PL.qs2[q]; }
-  });
-  int i2, j2;
-  decode_x<BC::R2a, DIAG>(xd, x, i2, j2);
-  return sT[r2 * KTL + (i2 + Sh::SH(A, 1)) * L + m] * sT[s2 * KTL + (j2 + Sh::SH(B, 1)) * L + m];
-}
 
-// stage-1 B operand: u = T^<r1>_{i1+sa}(l) T^<s1>_{j1+sb}(l), k = (g, l)
-template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ Real u1_value(const Real* sT, int y, int k) {
+// ---------------------------------------------------------------------------
+// pairs of a block: the non-diagonal pairs (i3, j3), j3 in [lo, hi), i3 < j3
+// (diagonal block) or i3 < R3a, enumerated j3-major; then the diagonal pairs
+// (j3, j3) of a diagonal block.  A batch is a run [t0, t0 + np) of one list.
+// ---------------------------------------------------------------------------
+template <int S, int P, int A, int B>
+__device__ __forceinline__ void pair_of(bool diag, int t, int lo, int& i3, int& j3) {
   using BC = Blk<S, P, A, B>;
-  using Sh = Shape<S, P>;
-  constexpr int L = BC::L, KTL = KT * L;
-  if (y >= BC::NY || k >= BC::K1) return Real(0);
-  const int g = k / L, l = k - g * L;
-  const int i1 = y % BC::R1a, j1 = y / BC::R1a;
-  int r1 = 0, s1 = 0;
-  static_for<BC::NG>([&](auto G) {
-    constexpr int gg = decltype(G)::value;
-    if (g == gg) { r1 = BC::PL.gr1[gg]; s1 = BC::PL.gs1[gg]; }
-  });
-  return sT[r1 * KTL + (i1 + Sh::SH(A, 0)) * L + l] * sT[s1 * KTL + (j1 + Sh::SH(B, 0)) * L + l];
+  if (diag) { i3 = lo + t; j3 = lo + t; return; }
+  if constexpr (A != B) {
+    j3 = lo + t / BC::R3a;
+    i3 = t % BC::R3a;
+  } else {
+    int j = lo;
+    while (t >= j) { t -= j; ++j; }
+    j3 = j;
+    i3 = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// stage-3 thread roles.  Thread t owns the point column (l, m) = t % L^2 for
-// all n, pair slot pi and q subset qs of every batch of the block; with
-// W3 = NP L^2 * QSPLIT <= 256 every thread has one fixed role, so the metric
-// fields of its column and q subset stay in registers for the whole block.
+// stage-3 thread roles.  A batch has W3 = NB NP L^2 point columns (pair slot,
+// l, m); QS q-subsets split the work further when W3 < 256.  When one round
+// covers all roles, every thread keeps the same (l, m) column for the whole
+// block, and its metric fields stay in registers.
 // ---------------------------------------------------------------------------
-template <int S, int P, int A, int B> struct S3Roles {
+template <int S, int P, typename Real, int A, int B> struct S3Roles {
   using BC = Blk<S, P, A, B>;
-  static constexpr int L = BC::L, QS = BC::QSPLIT;
+  using CF = Cfg<S, P, Real>;
+  static constexpr int L = BC::L, L2 = L * L;
+  static constexpr int W3 = CF::NBP * L2;
+  static constexpr int QS = imax(1, imin(BC::NQ, NTHREADS / W3));
+  static constexpr int ROUNDS = (W3 * QS + NTHREADS - 1) / NTHREADS;
   // distinct block field slots used by the terms of q subset qs
   static constexpr int nfs(int qs) {
     int seen[8] = {}, n = 0;
@@ -334,7 +328,6 @@ template <int S, int P, int A, int B> struct S3Roles {
     }
     return n;
   }
-  // s-th field slot of subset qs
   static constexpr int fsub(int qs, int s) {
     int seen[8] = {}, n = 0;
     for (int t = 0; t < BC::PL.nt; ++t) {
@@ -346,7 +339,6 @@ template <int S, int P, int A, int B> struct S3Roles {
     }
     return seen[s];
   }
-  // position of term tt's field within its subset
   static constexpr int fpos(int tt) {
     const int qs = BC::PL.tq[tt] % QS;
     for (int s = 0; s < nfs(qs); ++s)
@@ -358,251 +350,206 @@ template <int S, int P, int A, int B> struct S3Roles {
     for (int q = 0; q < QS; ++q) m = imax(m, nfs(q));
     return m;
   }();
-  static constexpr bool REGF = NFS * L <= 48;   // field column fits in registers
+  static constexpr bool REGF = ROUNDS == 1 && NFS * L <= DPG_REGF_MAX;   // field column fits in registers
+};
+
+// Stage-2 table operands of a wave's fixed x-tile kept in registers: when a
+// block's non-diagonal batch has at most one work item per wave.
+template <int S, int P, typename Real, int A, int B> struct Cache2 {
+  using BC = Blk<S, P, A, B>;
+  using CF = Cfg<S, P, Real>;
+  static constexpr bool ON = CF::NB * BC::NXT <= 4 && BC::NQ * BC::RPP <= DPG_C2_MAX;
+  static constexpr int N = ON ? BC::NQ * BC::RPP : 1;
 };
 
 template <int S, int P, typename Real, int A, int B> struct Regs {
-  using BC = Blk<S, P, A, B>;
-  using R3 = S3Roles<S, P, A, B>;
-  Real u2[BC::KS2 > 0 ? BC::KS2 : 1];   // stage-2 table operand of the wave's x-tile
-  Real u1[BC::KS1];                     // stage-1 table operand of the wave's y-tile
+  using R3 = S3Roles<S, P, Real, A, B>;
   Real fr[R3::REGF ? R3::NFS : 1][R3::REGF ? R3::L : 1];   // stage-3 metric fields
+  Real u2[Cache2<S, P, Real, A, B>::N];                      // stage-2 table operand
 };
 
-// ---------------------------------------------------------------------------
-// a batch of np pairs (i3[k], j3[k]) of block (A, B); wave-uniform
-// ---------------------------------------------------------------------------
-struct PairBatch {
-  int np;
-  int i3[4], j3[4];
-  __device__ __forceinline__ int ki(int k) const {
-    return k == 0 ? i3[0] : k == 1 ? i3[1] : k == 2 ? i3[2] : i3[3];
-  }
-  __device__ __forceinline__ int kj(int k) const {
-    return k == 0 ? j3[0] : k == 1 ? j3[1] : k == 2 ? j3[2] : j3[3];
-  }
-};
-
-// stage 3: A[(q, m)][(pi, l)] = sum_n c(l, m, n) T_i3(n) T_j3(n) for the pairs of pb
+// stage 3: A[pg][(q, m)][row(pi, l)] = sum_n c(l, m, n) T_i3(n) T_j3(n) for the batch's pairs
 template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, const PairBatch& pb) {
+__device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, bool diag, int t0,
+                                       int np, int lo, Real* sAb) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
-  using R3 = S3Roles<S, P, A, B>;
-  constexpr int L = Sh::L, L2 = L * L, KTL = KT * L;
-  constexpr int W3 = BC::NP * L2;
-  constexpr int QS = BC::QSPLIT;
+  using CF = Cfg<S, P, Real>;
+  using R3 = S3Roles<S, P, Real, A, B>;
+  using M = Mma<Real>;
+  constexpr int L = Sh::L, L2 = L * L, KTL = KT * L, QS = R3::QS, W3 = R3::W3;
   const Real* sT = static_cast<const Real*>(sm.T);
   const Real* sF = static_cast<const Real*>(sm.fld);
-  Real* sA = static_cast<Real*>(sm.A);
-  const int t = threadIdx.x;
-  if (t >= W3 * QS) return;
-  const int idx = t % W3;
-  const int qs = (W3 % 64 == 0) ? __builtin_amdgcn_readfirstlane(t / W3) : t / W3;
-  const int l = idx % L, m = (idx / L) % L;
-  const int pi = (L2 % 64 == 0) ? __builtin_amdgcn_readfirstlane(idx / L2) : idx / L2;
-  if (pi >= pb.np) return;
-  const int ka = pb.ki(pi) + Sh::SH(A, 2);
-  const int kb = pb.kj(pi) + Sh::SH(B, 2);
-  static_for<QS>([&](auto QQ) {
-    constexpr int qq = decltype(QQ)::value;
-    if (qs != qq) return;
-    Real acc[BC::NQ];
 #pragma unroll
-    for (int q = 0; q < BC::NQ; ++q) acc[q] = Real(0);
+  for (int rd = 0; rd < R3::ROUNDS; ++rd) {
+    const int it = threadIdx.x + rd * NTHREADS;
+    if (it >= W3 * QS) break;
+    const int idx = it % W3, qs = it / W3;
+    const int l = idx % L, m = (idx / L) % L, k = idx / L2;
+    if (k >= np) continue;
+    int i3, j3;
+    pair_of<S, P, A, B>(diag, t0 + k, lo, i3, j3);
+    const int pg = k / BC::NP, pi = k % BC::NP;
+    const int ka = i3 + Sh::SH(A, 2), kb = j3 + Sh::SH(B, 2);
+    Real* dst = sAb + pg * CF::AONE + m * 16 + M::crow(l & 3, pi * BC::RPP + (l >> 2));
+    static_for<QS>([&](auto QQ) {
+      constexpr int qq = decltype(QQ)::value;
+      if (qs != qq) return;
+      Real acc[BC::NQ];
 #pragma unroll
-    for (int n = 0; n < L; ++n) {
-      const Real ti0 = sT[ka * L + n], ti1 = sT[KTL + ka * L + n];
-      const Real tj0 = sT[kb * L + n], tj1 = sT[KTL + kb * L + n];
-      static_for<BC::PL.nt>([&](auto TT) {
-        constexpr int tt = decltype(TT)::value;
-        constexpr int q = BC::PL.tq[tt];
-        if constexpr (q % QS == qq) {
-          Real u = (BC::PL.t[tt].r[2] ? ti1 : ti0) * (BC::PL.t[tt].s[2] ? tj1 : tj0);
-          if constexpr (BC::PL.t[tt].sign < 0) u = -u;
-          Real f;
-          if constexpr (R3::REGF) f = rg.fr[R3::fpos(tt)][n];
-          else f = sF[(BC::PL.tf[tt] * L + n) * L2 + m * L + l];
-          acc[q] += u * f;
-        }
+      for (int q = 0; q < BC::NQ; ++q) acc[q] = Real(0);
+#pragma unroll
+      for (int n = 0; n < L; ++n) {
+        const Real ti0 = sT[ka * L + n], ti1 = sT[KTL + ka * L + n];
+        const Real tj0 = sT[kb * L + n], tj1 = sT[KTL + kb * L + n];
+        static_for<BC::PL.nt>([&](auto TT) {
+          constexpr int tt = decltype(TT)::value;
+          constexpr int q = BC::PL.tq[tt];
+          if constexpr (q % QS == qq) {
+            Real u = (BC::PL.t[tt].r[2] ? ti1 : ti0) * (BC::PL.t[tt].s[2] ? tj1 : tj0);
+            if constexpr (BC::PL.t[tt].sign < 0) u = -u;
+            Real f;
+            if constexpr (R3::REGF) f = rg.fr[R3::fpos(tt)][n];
+            else f = sF[(BC::PL.tf[tt] * L + n) * L2 + m * L + l];
+            acc[q] += u * f;
+          }
+        });
+      }
+      static_for<BC::NQ>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        if constexpr (q % QS == qq) dst[q * BC::LP * 16] = acc[q];
       });
-    }
-    static_for<BC::NQ>([&](auto Q) {
-      constexpr int q = decltype(Q)::value;
-      constexpr int row = BC::arow_q(q);
-      if constexpr (q % QS == qq) sA[(row + m) * NC2 + pi * L + l] = acc[q];
     });
-  });
-}
-
-// stage 2 (MFMA): B[g][(pi, l)][x] = sum_{(q,m) in g} A[(q,m)][(pi,l)] U2[(q,m)][x], x chunk xc
-template <int S, int P, typename Real, int A, int B, bool DIAG>
-__device__ __forceinline__ void stage2(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, int xc) {
-  using LD = Lds<S, P, Real>;
-  using BC = Blk<S, P, A, B>;
-  using M = Mma<Real>;
-  constexpr int L = BC::L;
-  constexpr int NXv = DIAG ? BC::NXD : BC::NX;
-  constexpr int NXPv = ru16(NXv);
-  constexpr int XS = imin(LD::XCH, BC::NXP);
-  constexpr int NCH = (NXPv + XS - 1) / XS;
-  constexpr bool CACHE2 = !DIAG && NCH == 1 && BC::NXP <= 64;
-  const Real* sT = static_cast<const Real*>(sm.T);
-  const Real* sA = static_cast<const Real*>(sm.A);
-  Real* sB = static_cast<Real*>(sm.B);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int xtiles = imin(XS, NXPv - xc) / 16;
-  for (int xt = wave; xt < xtiles; xt += 4) {
-    const int xl = xt * 16 + lr;           // x within the chunk (B-operand column)
-    const int x = xc + xl;
-    typename M::acc acc[BC::NG];
-#pragma unroll
-    for (int g = 0; g < BC::NG; ++g) acc[g] = typename M::acc{0, 0, 0, 0};
-    static_for<BC::NG>([&](auto GG) {
-      constexpr int G = decltype(GG)::value;
-      constexpr int KSG = BC::ks2(G), KG = BC::nqg(G) * L, KR = BC::krow0(G), KO = BC::koff2(G);
-#pragma unroll
-      for (int ks = 0; ks < KSG; ++ks) {
-        const int kk = 4 * ks + lk;
-        const Real a = kk < KG ? sA[(KR + kk) * NC2 + lr] : Real(0);
-        Real u;
-        if constexpr (CACHE2) u = rg.u2[KO + ks];
-        else u = u2_value<S, P, Real, A, B, DIAG, G>(sT, sm.xd, x, kk);
-        acc[G] = M::mac(a, u, acc[G]);
-      }
-    });
-#pragma unroll
-    for (int g = 0; g < BC::NG; ++g)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = M::crow(lk, r);
-        sB[bidx<XS>(g * NC2 + col, col, xl)] = acc[g][r];
-      }
   }
 }
 
-// stage 1 (MFMA) and the packed store: G[(i1,i2),(j1,j2)] for the pairs of pb, x chunk xc
+// stages 2 and 1 and the packed store for the work items of this wave in one batch
 template <int S, int P, typename Real, int A, int B, bool DIAG>
-__device__ __forceinline__ void stage1(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, const PairBatch& pb,
-                                       int xc, Real* __restrict__ outp) {
+__device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, int t0, int np, int lo,
+                                     const Real* sAb, Real* __restrict__ outp) {
   using Sh = Shape<S, P>;
-  using LD = Lds<S, P, Real>;
   using BC = Blk<S, P, A, B>;
+  using CF = Cfg<S, P, Real>;
   using M = Mma<Real>;
-  constexpr int L = BC::L;
+  constexpr int L = BC::L, LP = BC::LP, RPP = BC::RPP, NP = BC::NP, KTL = KT * L;
+  constexpr int XT = DIAG ? BC::NXDT : BC::NXT;
   constexpr int NXv = DIAG ? BC::NXD : BC::NX;
-  constexpr int NXPv = ru16(NXv);
-  constexpr int XS = imin(LD::XCH, BC::NXP);
-  constexpr bool CACHE1 = BC::NYT <= 4;
-  constexpr int XB = 4;
+  constexpr bool C2 = Cache2<S, P, Real, A, B>::ON && !DIAG;
+  constexpr int YB = imin(DPG_YB, BC::NYT), YCH = (BC::NYT + YB - 1) / YB;
   const Real* sT = static_cast<const Real*>(sm.T);
-  const Real* sB = static_cast<const Real*>(sm.B);
+  const Real* sU1 = static_cast<const Real*>(sm.U1);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int xtiles = imin(XS, NXPv - xc) / 16;
-  for (int yt = wave; yt < BC::NYT; yt += 4) {
-    const int y = yt * 16 + lr;
-    const bool yv = y < BC::NY;
-    const int i1 = y % BC::R1a, j1 = y / BC::R1a;
-    const int xrow = M::arow(lr);
-    for (int pi = 0; pi < pb.np; ++pi) {
-      const int Ib = Sh::OFF(A) + i1 + BC::R1a * BC::R2a * pb.ki(pi);
-      const int Jb = Sh::OFF(B) + j1 + BC::R1b * BC::R2b * pb.kj(pi);
-      for (int xt0 = 0; xt0 < xtiles; xt0 += XB) {
-        typename M::acc acc[XB];
+  for (int item = wave; item < CF::NB * XT; item += 4) {
+    const int pg = item / XT, xt = item % XT;
+    const int npg = imin(NP, np - pg * NP);
+    if (npg <= 0) continue;
+    // ---------------- stage 2: acc2[g] = C2 rows (pair, l) x 16 columns x ----------------
+    typename M::acc acc2[BC::NG];
 #pragma unroll
-        for (int c = 0; c < XB; ++c) acc[c] = typename M::acc{0, 0, 0, 0};
+    for (int g = 0; g < BC::NG; ++g) acc2[g] = typename M::acc{0, 0, 0, 0};
+    int ia = lk, jb = lk;
+    if constexpr (!C2) {
+      const int xs = xt * 16 + M::arow(lr);
+      int i2 = 0, j2 = 0;
+      if (xs < NXv) decode_x<BC::R2a, DIAG>(sm.xd, xs, i2, j2);
+      ia = (i2 + Sh::SH(A, 1)) * L + lk;
+      jb = (j2 + Sh::SH(B, 1)) * L + lk;
+    }
+    const Real* Ab = sAb + pg * CF::AONE + lane;
+    static_for<BC::NQ>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      constexpr int g = BC::PL.qg[q], r2 = BC::PL.qr2[q], s2 = BC::PL.qs2[q];
+      static_for<RPP>([&](auto KS) {
+        constexpr int ks = decltype(KS)::value;
+        const Real a = Ab[(q * LP + 4 * ks) * 16];
+        Real u;
+        if constexpr (C2) u = rg.u2[q * RPP + ks];
+        else u = sT[r2 * KTL + ia + 4 * ks] * sT[s2 * KTL + jb + 4 * ks];
+        acc2[g] = M::mac(a, u, acc2[g]);
+      });
+    });
+    // ---------------- stage 1 and store ----------------
+    // x of this lane's accumulator register r: xt * 16 + lk + 4 r
+    int xi2[4], xj2[4];
+    bool xv[4];
 #pragma unroll
-        for (int ks = 0; ks < BC::KS1; ++ks) {
-          const int k = 4 * ks + lk;
-          const int g = k / L, l = k - g * L;
-          const int col = pi * L + l;
-          Real u;
-          if constexpr (CACHE1) u = rg.u1[ks];
-          else u = u1_value<S, P, Real, A, B>(sT, y, k);
+    for (int r = 0; r < 4; ++r) {
+      const int s = xt * 16 + lk + 4 * r;
+      xv[r] = s < NXv;
+      xi2[r] = 0;
+      xj2[r] = 0;
+      if (xv[r]) decode_x<BC::R2a, DIAG>(sm.xd, s, xi2[r], xj2[r]);
+    }
+    static_for<NP>([&](auto PI) {
+      constexpr int pi = decltype(PI)::value;
+      if (pi >= npg) return;
+      int i3, j3;
+      pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, i3, j3);
+      const int Ib = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
+      const int Jb = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
+      static_for<YCH>([&](auto YC) {
+        constexpr int yc = decltype(YC)::value;
+        typename M::acc acc1[YB];
 #pragma unroll
-          for (int c = 0; c < XB; ++c) {
-            if (xt0 + c < xtiles) {
-              const Real a = (BC::K1 % 4 == 0 || k < BC::K1)
-                                 ? sB[bidx<XS>(g * NC2 + col, col, (xt0 + c) * 16 + xrow)] : Real(0);
-              acc[c] = M::mac(a, u, acc[c]);
-            }
-          }
-        }
+        for (int c = 0; c < YB; ++c) acc1[c] = typename M::acc{0, 0, 0, 0};
+        static_for<BC::NG>([&](auto G) {
+          constexpr int g = decltype(G)::value;
+          constexpr int r1 = BC::PL.gr1[g], s1 = BC::PL.gs1[g];
+          static_for<RPP>([&](auto RHO) {
+            constexpr int rho = decltype(RHO)::value;
+            const Real a = acc2[g][pi * RPP + rho];
+            static_for<YB>([&](auto YY) {
+              constexpr int yt = yc * YB + decltype(YY)::value;
+              if constexpr (yt < BC::NYT) {
+                Real u;
+                if constexpr (CF::U1TAB) {
+                  u = sU1[((g * RPP + rho) * BC::NYT + yt) * 64 + lane];
+                } else {
+                  const int y = yt * 16 + lr;
+                  const int yy = y < BC::NY ? y : 0;
+                  const int i1 = yy % BC::R1a, j1 = yy / BC::R1a;
+                  u = sT[r1 * KTL + (i1 + Sh::SH(A, 0)) * L + lk + 4 * rho] *
+                      sT[s1 * KTL + (j1 + Sh::SH(B, 0)) * L + lk + 4 * rho];
+                }
+                acc1[decltype(YY)::value] = M::mac(a, u, acc1[decltype(YY)::value]);
+              }
+            });
+          });
+        });
+        // packed store: register r of lane (lk, lr) holds G[x = xt*16 + lk + 4r][y = yt*16 + lr]
+        static_for<YB>([&](auto YY) {
+          constexpr int yt = yc * YB + decltype(YY)::value;
+          if constexpr (yt < BC::NYT) {
+            const int y = yt * 16 + lr;
+            if (y < BC::NY) {
+              const int i1 = y % BC::R1a, j1 = y / BC::R1a;
 #pragma unroll
-        for (int c = 0; c < XB; ++c) {
-          if (xt0 + c < xtiles) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int s = xc + (xt0 + c) * 16 + lk + 4 * r;
-              if (yv && s < NXv) {
-                int i2, j2;
-                decode_x<BC::R2a, DIAG>(sm.xd, s, i2, j2);
-                if (!DIAG || i2 < j2 || i1 <= j1) {
-                  const int I = Ib + BC::R1a * i2;
-                  const int J = Jb + BC::R1b * j2;
-                  outp[I + J * (J + 1) / 2] = acc[c][r];
+              for (int r = 0; r < 4; ++r) {
+                if (xv[r] && (!DIAG || xi2[r] < xj2[r] || i1 <= j1)) {
+                  const int I = Ib + i1 + BC::R1a * xi2[r];
+                  const int J = Jb + j1 + BC::R1b * xj2[r];
+                  outp[I + J * (J + 1) / 2] = acc1[decltype(YY)::value][r];
                 }
               }
             }
           }
-        }
-      }
-    }
+        });
+      });
+    });
   }
 }
-
-// Pair batches of a block: off-diagonal pairs (i3, j3), j3 in [j3_lo, j3_hi),
-// i3 < j3 (diagonal block) or i3 < R3a, NP at a time; then the diagonal
-// pairs (j3, j3) of a diagonal block, NP at a time.
-template <int S, int P, int A, int B> struct PairCursor {
-  using BC = Blk<S, P, A, B>;
-  int ci, cj, hi, dj;
-  __device__ __forceinline__ int rows(int j) const { return A == B ? j : BC::R3a; }
-  __device__ __forceinline__ void skip() { while (cj < hi && ci >= rows(cj)) { ++cj; ci = 0; } }
-  __device__ __forceinline__ PairCursor(int lo, int hi_) : ci(0), cj(lo), hi(hi_), dj(lo) { skip(); }
-  // next batch; returns false when done; *diag tells which x-list it uses
-  __device__ __forceinline__ bool next(PairBatch& pb, bool& diag) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { pb.i3[k] = 0; pb.j3[k] = 0; }
-    pb.np = 0;
-    if (cj < hi) {
-      diag = false;
-#pragma unroll
-      for (int k = 0; k < BC::NP; ++k) {
-        if (cj < hi) {
-          pb.i3[k] = ci;
-          pb.j3[k] = cj;
-          pb.np = k + 1;
-          ++ci;
-          skip();
-        }
-      }
-      return true;
-    }
-    if (A == B && dj < hi) {
-      diag = true;
-      pb.np = imin(BC::NP, hi - dj);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { pb.i3[k] = dj + k; pb.j3[k] = dj + k; }
-      dj += BC::NP;
-      return true;
-    }
-    return false;
-  }
-};
 
 template <int S, int P, typename Real, int A, int B>
 __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs sm, int j3_lo, int j3_hi,
                                           Real* __restrict__ outp) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
-  using LD = Lds<S, P, Real>;
-  using R3 = S3Roles<S, P, A, B>;
-  constexpr int L = Sh::L, L2 = L * L, L3 = L2 * L;
+  using CF = Cfg<S, P, Real>;
+  using R3 = S3Roles<S, P, Real, A, B>;
+  using M = Mma<Real>;
+  constexpr int L = Sh::L, L2 = L * L, L3 = L2 * L, KTL = KT * L, RPP = BC::RPP;
   Real* sF = static_cast<Real*>(sm.fld);
   const Real* sT = static_cast<const Real*>(sm.T);
   const int tid = threadIdx.x;
@@ -626,32 +573,37 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       sF[(f * L + n) * L2 + m * L + l] = static_cast<Real>(v);
     });
   }
-
-  // ---------------- table operands of this wave's tiles, kept in registers ----------------
-  Regs<S, P, Real, A, B> rg;
-  {
-    const int x = wave * 16 + lr;
-    static_for<BC::NG>([&](auto GG) {
-      constexpr int G = decltype(GG)::value;
-      constexpr int KSG = BC::ks2(G), KO = BC::koff2(G);
-#pragma unroll
-      for (int ks = 0; ks < KSG; ++ks)
-        rg.u2[KO + ks] = u2_value<S, P, Real, A, B, false, G>(sT, sm.xd, x, 4 * ks + lk);
-    });
-    const int y = wave * 16 + lr;
-#pragma unroll
-    for (int ks = 0; ks < BC::KS1; ++ks) rg.u1[ks] = u1_value<S, P, Real, A, B>(sT, y, 4 * ks + lk);
+  // ---------------- stage-1 table operand of this block ----------------
+  if constexpr (CF::U1TAB) {
+    Real* sU1 = static_cast<Real*>(sm.U1);
+    constexpr int N = BC::NG * RPP * BC::NYT * 64;
+    for (int i = tid; i < N; i += NTHREADS) {
+      const int ln = i & 63, t = i >> 6;
+      const int yt = t % BC::NYT, grh = t / BC::NYT, rho = grh % RPP, g = grh / RPP;
+      const int y = yt * 16 + (ln & 15), l = 4 * rho + (ln >> 4);
+      Real v = Real(0);
+      if (y < BC::NY && l < L) {
+        int r1 = 0, s1 = 0;
+        static_for<BC::NG>([&](auto GG) {
+          constexpr int gg = decltype(GG)::value;
+          if (g == gg) { r1 = BC::PL.gr1[gg]; s1 = BC::PL.gs1[gg]; }
+        });
+        const int i1 = y % BC::R1a, j1 = y / BC::R1a;
+        v = sT[r1 * KTL + (i1 + Sh::SH(A, 0)) * L + l] * sT[s1 * KTL + (j1 + Sh::SH(B, 0)) * L + l];
+      }
+      sU1[i] = v;
+    }
   }
   __syncthreads();
   if (*sm.bad) return true;
 
+  Regs<S, P, Real, A, B> rg;
   // ---------------- this thread's stage-3 field column, kept in registers ----------------
   if constexpr (R3::REGF) {
-    constexpr int W3 = BC::NP * L2;
-    if (tid < W3 * BC::QSPLIT) {
-      const int idx = tid % W3, qs = tid / W3;
+    if (tid < R3::W3 * R3::QS) {
+      const int idx = tid % R3::W3, qs = tid / R3::W3;
       const int l = idx % L, m = (idx / L) % L;
-      static_for<BC::QSPLIT>([&](auto QQ) {
+      static_for<R3::QS>([&](auto QQ) {
         constexpr int qq = decltype(QQ)::value;
         if (qs == qq) {
           static_for<R3::nfs(qq)>([&](auto SS) {
@@ -663,46 +615,85 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       });
     }
   }
-
-  // ---------------- pipelined batches ----------------
-  // [stage 2 (t)] barrier [stage 3 (t+1), stage 1 (t)] barrier ...
-  constexpr int NXP_ND = BC::NXP;
-  constexpr int XS = imin(LD::XCH, BC::NXP);
-  PairCursor<S, P, A, B> cur(j3_lo, j3_hi);
-  PairBatch pb, pn;
-  bool dg = false, dn = false;
-  bool have = cur.next(pb, dg);
-  if (have) stage3<S, P, Real, A, B>(sm, rg, pb);
-  __syncthreads();
-  while (have) {
-    const bool have_next = cur.next(pn, dn);
-    const int nxp = dg ? ru16(BC::NXD) : NXP_ND;
-    for (int xc = 0; xc < nxp; xc += XS) {
-      if (dg) stage2<S, P, Real, A, B, true>(sm, rg, xc);
-      else stage2<S, P, Real, A, B, false>(sm, rg, xc);
-      __syncthreads();
-      if (xc + XS >= nxp && have_next) stage3<S, P, Real, A, B>(sm, rg, pn);
-      if (dg) stage1<S, P, Real, A, B, true>(sm, rg, pb, xc, outp);
-      else stage1<S, P, Real, A, B, false>(sm, rg, pb, xc, outp);
-      __syncthreads();
-    }
-    pb = pn;
-    dg = dn;
-    have = have_next;
+  // ---------------- stage-2 table operand of this wave's fixed x-tile ----------------
+  if constexpr (Cache2<S, P, Real, A, B>::ON) {
+    const int xt = wave % BC::NXT;
+    const int xs = xt * 16 + M::arow(lr);
+    int i2 = 0, j2 = 0;
+    if (xs < BC::NX) decode_x<BC::R2a, false>(sm.xd, xs, i2, j2);
+    const int ia = (i2 + Sh::SH(A, 1)) * L + lk, jb = (j2 + Sh::SH(B, 1)) * L + lk;
+    static_for<BC::NQ>([&](auto Q) {
+      constexpr int q = decltype(Q)::value;
+      static_for<RPP>([&](auto KS) {
+        constexpr int ks = decltype(KS)::value;
+        rg.u2[q * RPP + ks] = sT[BC::PL.qr2[q] * KTL + ia + 4 * ks] * sT[BC::PL.qs2[q] * KTL + jb + 4 * ks];
+      });
+    });
   }
-  (void)sF;
+
+  // ---------------- batches of pairs ----------------
+  // ABUF == 2: [stage 3 (b+1) | stages 2+1 (b)] barrier ...
+  // ABUF == 1: [stages 2+1 (b)] barrier [stage 3 (b+1)] barrier ...
+  constexpr int NBP = CF::NBP;
+  const int n_nd = A != B ? BC::R3a * (j3_hi - j3_lo) : (j3_hi * (j3_hi - 1) - j3_lo * (j3_lo - 1)) / 2;
+  const int n_d = A == B ? j3_hi - j3_lo : 0;
+  const int nb_nd = (n_nd + NBP - 1) / NBP;
+  const int nbt = nb_nd + (n_d + NBP - 1) / NBP;
+  auto batch = [&](int b, bool& dg, int& t0, int& np) {
+    if (b < nb_nd) { dg = false; t0 = b * NBP; np = imin(NBP, n_nd - t0); }
+    else { dg = true; t0 = (b - nb_nd) * NBP; np = imin(NBP, n_d - t0); }
+  };
+  Real* sA = static_cast<Real*>(sm.A);
+  constexpr int ASTRIDE = CF::NB * CF::AONE;
+  if (nbt > 0) {
+    bool dg; int t0, np;
+    batch(0, dg, t0, np);
+    stage3<S, P, Real, A, B>(sm, rg, dg, t0, np, j3_lo, sA);
+  }
+  __syncthreads();
+  for (int b = 0; b < nbt; ++b) {
+    bool dg; int t0, np;
+    batch(b, dg, t0, np);
+    const Real* cur = sA + (CF::ABUF == 2 ? (b & 1) * ASTRIDE : 0);
+    if constexpr (CF::ABUF == 2) {
+      if (b + 1 < nbt) {
+        bool dn; int tn, nn;
+        batch(b + 1, dn, tn, nn);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, sA + ((b + 1) & 1) * ASTRIDE);
+      }
+    }
+    if (dg) work<S, P, Real, A, B, true>(sm, rg, t0, np, j3_lo, cur, outp);
+    else work<S, P, Real, A, B, false>(sm, rg, t0, np, j3_lo, cur, outp);
+    __syncthreads();
+    if constexpr (CF::ABUF == 1) {
+      if (b + 1 < nbt) {
+        bool dn; int tn, nn;
+        batch(b + 1, dn, tn, nn);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, sA);
+        __syncthreads();
+      }
+    }
+  }
+  (void)lr;
   return false;
 }
 
+// Waves per SIMD the register allocation must allow: two when the LDS layout
+// leaves room for two workgroups per CU and the order is low enough for the
+// register state to fit without spilling, else one.
+template <int S, int P, typename Real> constexpr int min_waves() {
+  return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && npoints(S, P) <= DPG_MINW2_LMAX) ? 2 : 1;
+}
+
 template <int S, int P, typename Real>
-__global__ void __launch_bounds__(NTHREADS) k_general(GeneralArgs ga) {
+__global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general(GeneralArgs ga) {
   using Sh = Shape<S, P>;
-  using LD = Lds<S, P, Real>;
+  using CF = Cfg<S, P, Real>;
   constexpr int L = Sh::L;
-  __shared__ Real s_fld[LD::FLD_LEN];
-  __shared__ Real s_A[LD::A_LEN];
-  __shared__ Real s_B[LD::B_LEN];
-  __shared__ Real s_T[LD::T_LEN];
+  __shared__ Real s_fld[CF::FLD_LEN];
+  __shared__ Real s_A[CF::ABUF * CF::NB * CF::AONE];
+  __shared__ Real s_U1[CF::U1TAB ? CF::U1_LEN : 1];
+  __shared__ Real s_T[CF::T_LEN];
   __shared__ double s_z[L], s_w[L], s_X[24];
   __shared__ unsigned char s_xd[2 * 80];
   __shared__ int s_bad;
@@ -717,7 +708,9 @@ __global__ void __launch_bounds__(NTHREADS) k_general(GeneralArgs ga) {
   const int s_lo = grp * G, s_hi = imin(Sh::NSLAB, s_lo + G);
 
   const Real* tR = static_cast<const Real*>(ga.tabR);
-  for (int i = tid; i < LD::T_LEN; i += NTHREADS) s_T[i] = tR[2 * L + i];
+  for (int i = tid; i < CF::T_LEN; i += NTHREADS) s_T[i] = i < 2 * KT * L ? tR[2 * L + i] : Real(0);
+  // stage-3 output buffers: the padding rows (m >= L) and columns (l >= L) stay zero
+  for (int i = tid; i < CF::ABUF * CF::NB * CF::AONE; i += NTHREADS) s_A[i] = Real(0);
   if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
   const int ng = ga.geom_kind == 1 ? 12 : 24;
   if (tid < ng) s_X[tid] = ga.geom[e * ng + tid];
@@ -731,9 +724,8 @@ __global__ void __launch_bounds__(NTHREADS) k_general(GeneralArgs ga) {
   if (tid == 0) s_bad = 0;
   __syncthreads();
 
-  SmemPtrs sm{s_fld, s_A, s_B, s_T, s_z, s_w, s_X, s_xd, &s_bad};
+  SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_z, s_w, s_X, s_xd, &s_bad};
   Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
-
   // component b owns slabs [slab0(b), slab0(b) + R3(b)); visit the blocks (a, b), a <= b,
   // for the j3 range of every component the slab group touches
   bool bad = false;
