@@ -94,6 +94,9 @@ constexpr int NTHREADS = 256;
 #ifndef DPG_YB
 #define DPG_YB 4
 #endif
+#ifndef DPG_U1R_MAX
+#define DPG_U1R_MAX 0
+#endif
 #ifndef DPG_MINW2_LMAX
 #define DPG_MINW2_LMAX 8
 #endif
@@ -284,6 +287,22 @@ __device__ __forceinline__ void decode_x(const unsigned char* xd, int s, int& i2
 
 
 // ---------------------------------------------------------------------------
+// output stores through a raw buffer descriptor over one element's packed
+// matrix (gfx9 descriptor word 3); offsets at or past the range are dropped
+// ---------------------------------------------------------------------------
+template <typename Real>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(Real* p, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, int(n * (long long)sizeof(Real)), 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_out(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void store_out(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // pairs of a block: the non-diagonal pairs (i3, j3), j3 in [lo, hi), i3 < j3
 // (diagonal block) or i3 < R3a, enumerated j3-major; then the diagonal pairs
 // (j3, j3) of a diagonal block.  A batch is a run [t0, t0 + np) of one list.
@@ -362,10 +381,20 @@ template <int S, int P, typename Real, int A, int B> struct Cache2 {
   static constexpr int N = ON ? BC::NQ * BC::RPP : 1;
 };
 
+// Stage-1 table operands of every y-tile kept in registers (all waves hold the
+// same values) when they are few enough.
+template <int S, int P, int A, int B> struct Cache1 {
+  using BC = Blk<S, P, A, B>;
+  static constexpr int N0 = BC::NG * BC::RPP * BC::NYT;
+  static constexpr bool ON = N0 <= DPG_U1R_MAX;
+  static constexpr int N = ON ? N0 : 1;
+};
+
 template <int S, int P, typename Real, int A, int B> struct Regs {
   using R3 = S3Roles<S, P, Real, A, B>;
   Real fr[R3::REGF ? R3::NFS : 1][R3::REGF ? R3::L : 1];   // stage-3 metric fields
   Real u2[Cache2<S, P, Real, A, B>::N];                      // stage-2 table operand
+  Real u1[Cache1<S, P, A, B>::N];                            // stage-1 table operand
 };
 
 // stage 3: A[pg][(q, m)][row(pi, l)] = sum_n c(l, m, n) T_i3(n) T_j3(n) for the batch's pairs
@@ -441,6 +470,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rsrc = out_rsrc(outp, packed_len(S, P));
   for (int item = wave; item < CF::NB * XT; item += 4) {
     const int pg = item / XT, xt = item % XT;
     const int npg = imin(NP, np - pg * NP);
@@ -504,7 +534,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
               constexpr int yt = yc * YB + decltype(YY)::value;
               if constexpr (yt < BC::NYT) {
                 Real u;
-                if constexpr (CF::U1TAB) {
+                if constexpr (Cache1<S, P, A, B>::ON) {
+                  u = rg.u1[(g * RPP + rho) * BC::NYT + yt];
+                } else if constexpr (CF::U1TAB) {
                   u = sU1[((g * RPP + rho) * BC::NYT + yt) * 64 + lane];
                 } else {
                   const int y = yt * 16 + lr;
@@ -518,21 +550,22 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
             });
           });
         });
-        // packed store: register r of lane (lk, lr) holds G[x = xt*16 + lk + 4r][y = yt*16 + lr]
+        // packed store: register r of lane (lk, lr) holds G[x = xt*16 + lk + 4r][y = yt*16 + lr].
+        // Buffer stores without branches: a lane with nothing to store gets an
+        // offset past the element's range, which the buffer unit discards.
         static_for<YB>([&](auto YY) {
           constexpr int yt = yc * YB + decltype(YY)::value;
           if constexpr (yt < BC::NYT) {
             const int y = yt * 16 + lr;
-            if (y < BC::NY) {
-              const int i1 = y % BC::R1a, j1 = y / BC::R1a;
+            const bool yv = y < BC::NY;
+            const int i1 = y % BC::R1a, j1 = y / BC::R1a;
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                if (xv[r] && (!DIAG || xi2[r] < xj2[r] || i1 <= j1)) {
-                  const int I = Ib + i1 + BC::R1a * xi2[r];
-                  const int J = Jb + j1 + BC::R1b * xj2[r];
-                  outp[I + J * (J + 1) / 2] = acc1[decltype(YY)::value][r];
-                }
-              }
+            for (int r = 0; r < 4; ++r) {
+              const bool ok = yv && xv[r] && (!DIAG || xi2[r] < xj2[r] || i1 <= j1);
+              const unsigned I = unsigned(Ib + i1 + BC::R1a * xi2[r]);
+              const unsigned J = unsigned(Jb + j1 + BC::R1b * xj2[r]);
+              const int off = ok ? int((I + ((J * (J + 1)) >> 1)) * sizeof(Real)) : 0x7fffffff;
+              store_out(acc1[decltype(YY)::value][r], rsrc, off);
             }
           }
         });
@@ -627,6 +660,25 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       static_for<RPP>([&](auto KS) {
         constexpr int ks = decltype(KS)::value;
         rg.u2[q * RPP + ks] = sT[BC::PL.qr2[q] * KTL + ia + 4 * ks] * sT[BC::PL.qs2[q] * KTL + jb + 4 * ks];
+      });
+    });
+  }
+
+  // ---------------- stage-1 table operands of all y-tiles ----------------
+  if constexpr (Cache1<S, P, A, B>::ON) {
+    static_for<BC::NG>([&](auto G) {
+      constexpr int g = decltype(G)::value;
+      static_for<RPP>([&](auto RHO) {
+        constexpr int rho = decltype(RHO)::value;
+        static_for<BC::NYT>([&](auto YT) {
+          constexpr int yt = decltype(YT)::value;
+          const int y = yt * 16 + lr;
+          const int yy = y < BC::NY ? y : 0;
+          const int i1 = yy % BC::R1a, j1 = yy / BC::R1a;
+          rg.u1[(g * RPP + rho) * BC::NYT + yt] =
+              sT[BC::PL.gr1[g] * KTL + (i1 + Sh::SH(A, 0)) * L + lk + 4 * rho] *
+              sT[BC::PL.gs1[g] * KTL + (j1 + Sh::SH(B, 0)) * L + lk + 4 * rho];
+        });
       });
     });
   }
