@@ -191,6 +191,7 @@ def main():
     torch.cuda.empty_cache()
     if a.extra:
         extra["batched_mixed_50000"] = run_mixed_full(ctx, dpg, stream)
+        extra["scaling"] = run_scaling(ctx, dpg, stream)
     serving = None
     if a.serve_seconds > 0:
         serving = run_serving(ctx, dpg, a.serve_seconds)
@@ -274,6 +275,45 @@ def run_extra(ctx, dpg, stream, E, X, out64):
     del ob
     torch.cuda.empty_cache()
     return res
+
+
+def run_scaling(ctx, dpg, stream, out_bytes=2 << 30):
+    """Time per element against the order: the general path on perturbed hexes
+    (H1) and the reduced path on affine elements (H(curl)), p = 2..11, FP64,
+    with about out_bytes of output per launch (at most 4096 elements).  The
+    slopes of log(time/element) over log p, fitted on p >= 6, are set beside
+    the algorithmic exponents: flops ~ p^7 (general), output ~ p^6 (both)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    rows = {"general_H1": [], "reduced_HCURL": []}
+    for key, space, kind in (("general_H1", "H1", "trilinear"), ("reduced_HCURL", "HCURL", "affine")):
+        for p in range(2, 12):
+            m = dpg.packed_len(space, p)
+            n = int(max(16, min(4096, out_bytes // (m * 8))))
+            if kind == "trilinear":
+                g = torch.from_numpy(meshgen.perturbed_hexes(n, seed=7)).cuda()
+            else:
+                g = torch.from_numpy(meshgen.affine_parallelepipeds(n, seed=7)).cuda()
+            o = torch.empty(n * m, dtype=torch.float64, device="cuda")
+            w, per = time_launches(lambda: ctx.gram(space, p, g, kind=kind, out=o, stream=stream), 5, 2, stream)
+            us = float(np.mean(per)) * 1e3 / n
+            rows[key].append({"p": p, "n_elem": n, "us_per_elem": round(us, 4),
+                              "mflop_per_elem": round(dpg.general_flops(space, p) / 1e6, 3),
+                              "mb_per_elem": round(m * 8 / 1e6, 4)})
+            del o, g
+        torch.cuda.empty_cache()
+    fit = {}
+    for key, r in rows.items():
+        sel = [x for x in r if x["p"] >= 6]
+        lp = np.log([x["p"] for x in sel])
+        fit[key] = {"time_exponent": round(float(np.polyfit(lp, np.log([x["us_per_elem"] for x in sel]), 1)[0]), 2),
+                    "output_exponent": round(float(np.polyfit(lp, np.log([x["mb_per_elem"] for x in sel]), 1)[0]), 2)}
+        if key.startswith("general"):
+            fit[key]["flop_exponent"] = round(float(np.polyfit(lp, np.log([x["mflop_per_elem"] for x in sel]), 1)[0]), 2)
+    log(f"[bench] scaling fit (p >= 6): {fit}")
+    return {"rows": rows, "fit_p_ge_6": fit}
 
 
 def run_mixed_full(ctx, dpg, stream, n_elem=50000, chunk_bytes=48 << 30):

@@ -57,47 +57,45 @@ __device__ __forceinline__ void sfor(F&& f) {
   }(std::make_integer_sequence<int, N>{});
 }
 
-// The part of column J = (b; j1, j2, j3) that lies in component A: planes of
-// fixed i3, each R1a R2a consecutive rows.  Planes outside the direction-3 band
-// are zero; inside, rows outside the direction-1/2 bands are zero.
+// Value of row I of column J = (b; j1, j2, j3) when I lies in component A
+// (loc = I - OFF(A)): sum over the block's terms of coef * F1 F2 F3, zero
+// outside the band of any direction.
 template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ void column_block(const Real* sF, const Real* coef, int J, int j1, int j2, int j3,
-                                             Real* __restrict__ col, int lane) {
+__device__ __forceinline__ Real entry(const Real* sF, const Real* coef, int loc, int b1, int b2, int b3) {
   using Sh = AShape<S, P>;
   constexpr Plan PL = APlan<S, A, B>::PL;
-  constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1), R3a = Sh::R(A, 2);
-  constexpr int PLANE = R1a * R2a;
-  const int b1 = j1 + Sh::SH(B, 0), b2 = j2 + Sh::SH(B, 1), b3 = j3 + Sh::SH(B, 2);
-  for (int i3 = 0; i3 < R3a; ++i3) {
-    const int I0 = Sh::OFF(A) + PLANE * i3;
-    if (I0 > J) break;
-    const int Iend = (I0 + PLANE - 1 < J) ? I0 + PLANE - 1 : J;   // inclusive
-    const int a3 = i3 + Sh::SH(A, 2);
-    if (!band(a3, b3)) {
-      for (int I = I0 + lane; I <= Iend; I += 64) col[I] = Real(0);
-      continue;
-    }
-    // direction-3 factor of every term, uniform over the plane
-    Real w3[PL.nt];
+  constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1);
+  const int i1 = loc % R1a, t12 = loc / R1a;
+  const int i2 = t12 % R2a, i3 = t12 / R2a;
+  const int a1 = i1 + Sh::SH(A, 0), a2 = i2 + Sh::SH(A, 1), a3 = i3 + Sh::SH(A, 2);
+  Real v = Real(0);
+  if (band(a1, b1) && band(a2, b2) && band(a3, b3)) {
     sfor<PL.nt>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      w3[t] = coef[t] * sF[((2 * PL.t[t].r[2] + PL.t[t].s[2]) * KT + a3) * KT + b3];
+      const Real f1 = sF[((2 * PL.t[t].r[0] + PL.t[t].s[0]) * KT + a1) * KT + b1];
+      const Real f2 = sF[((2 * PL.t[t].r[1] + PL.t[t].s[1]) * KT + a2) * KT + b2];
+      const Real f3 = sF[((2 * PL.t[t].r[2] + PL.t[t].s[2]) * KT + a3) * KT + b3];
+      v += coef[t] * f1 * f2 * f3;
     });
-    for (int I = I0 + lane; I <= Iend; I += 64) {
-      const int loc = I - I0;
-      const int i1 = loc % R1a, i2 = loc / R1a;
-      const int a1 = i1 + Sh::SH(A, 0), a2 = i2 + Sh::SH(A, 1);
-      Real v = Real(0);
-      if (band(a1, b1) && band(a2, b2)) {
-        sfor<PL.nt>([&](auto T) {
-          constexpr int t = decltype(T)::value;
-          const Real f1 = sF[((2 * PL.t[t].r[0] + PL.t[t].s[0]) * KT + a1) * KT + b1];
-          const Real f2 = sF[((2 * PL.t[t].r[1] + PL.t[t].s[1]) * KT + a2) * KT + b2];
-          v += w3[t] * f1 * f2;
-        });
-      }
-      col[I] = v;
-    }
+  }
+  return v;
+}
+
+// Column J = (b; j1, j2, j3): rows 0..J, walked contiguously (64 consecutive
+// entries per store instruction across planes and components).
+template <int S, int P, typename Real, int B>
+__device__ __forceinline__ void column(const Real* sF, const Real (*sC)[3][10], int J, int j1, int j2, int j3,
+                                       Real* __restrict__ col, int lane) {
+  using Sh = AShape<S, P>;
+  const int b1 = j1 + Sh::SH(B, 0), b2 = j2 + Sh::SH(B, 1), b3 = j3 + Sh::SH(B, 2);
+  for (int I = lane; I <= J; I += 64) {
+    Real v = Real(0);
+    sfor<B + 1>([&](auto AA) {
+      constexpr int a = decltype(AA)::value;
+      constexpr int lo = Sh::OFF(a), hi = Sh::OFF(a + 1);
+      if (I >= lo && I < hi) v = entry<S, P, Real, a, B>(sF, &sC[a][B][0], I - lo, b1, b2, b3);
+    });
+    col[I] = v;
   }
 }
 
@@ -171,28 +169,48 @@ __global__ void __launch_bounds__(NT_AFF) k_affine(GeneralArgs ga) {
   const bool bad = s_bad != 0;
   const int lane = tid & 63, wave = tid >> 6;
 
-  // columns of the slab group, component by component
-  sfor<Sh::NC>([&](auto BB) {
-    constexpr int b = decltype(BB)::value;
-    constexpr int R1b = Sh::R(b, 0), R2b = Sh::R(b, 1);
-    constexpr int NCOL = R1b * R2b;
-    const int lo = (s_lo > Sh::slab0(b) ? s_lo : Sh::slab0(b)) - Sh::slab0(b);
-    const int hi = (s_hi < Sh::slab0(b) + Sh::R(b, 2) ? s_hi : Sh::slab0(b) + Sh::R(b, 2)) - Sh::slab0(b);
-    for (int c = lo * NCOL + wave; c < hi * NCOL; c += NT_AFF / 64) {
-      const int j3 = c / NCOL, r = c % NCOL;
-      const int j1 = r % R1b, j2 = r / R1b;
-      const int J = Sh::OFF(b) + c;
-      Real* col = outp + int64_t(J) * (J + 1) / 2;
-      if (bad) {
-        for (int I = lane; I <= J; I += 64) col[I] = Real(0);
-        continue;
-      }
-      sfor<b + 1>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        column_block<S, P, Real, a, b>(s_F, &s_C[a][b][0], J, j1, j2, j3, col, lane);
-      });
+  // Columns of the slab group form one contiguous packed range [J0, J1).
+  // Each wave takes a contiguous run of columns holding about a quarter of the
+  // range's entries, so neighbouring columns are written back to back by the
+  // same wave.
+  auto colstart = [&](int slab) {   // first column J of a slab (or the end)
+    int o = 0;
+    int J = 0;
+    sfor<Sh::NC>([&](auto CC) {
+      constexpr int c = decltype(CC)::value;
+      constexpr int n = Sh::R(c, 2), w = Sh::R(c, 0) * Sh::R(c, 1);
+      if (slab >= o && slab < o + n) J = Sh::OFF(c) + (slab - o) * w;
+      o += n;
+    });
+    return slab >= Sh::NSLAB ? int(Sh::OFF(Sh::NC)) : J;
+  };
+  const int J0 = colstart(s_lo), J1 = colstart(s_hi);
+  const double E0 = 0.5 * double(J0) * (J0 + 1), E1 = 0.5 * double(J1) * (J1 + 1);
+  // first column whose entries start at or after packed offset e: J (J+1)/2 >= e
+  auto col_at = [&](double e) {
+    int J = int(floor((sqrt(8.0 * e + 1.0) - 1.0) * 0.5));
+    while (0.5 * double(J) * (J + 1) < e) ++J;
+    while (J > 0 && 0.5 * double(J - 1) * J >= e) --J;
+    return J < J0 ? J0 : (J > J1 ? J1 : J);
+  };
+  const int Jw0 = wave == 0 ? J0 : col_at(E0 + (E1 - E0) * wave / 4.0);
+  const int Jw1 = wave == 3 ? J1 : col_at(E0 + (E1 - E0) * (wave + 1) / 4.0);
+  for (int J = Jw0; J < Jw1; ++J) {
+    Real* col = outp + int64_t(J) * (J + 1) / 2;
+    if (bad) {
+      for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+      continue;
     }
-  });
+    sfor<Sh::NC>([&](auto BB) {
+      constexpr int b = decltype(BB)::value;
+      constexpr int R1b = Sh::R(b, 0), R2b = Sh::R(b, 1);
+      if (J >= Sh::OFF(b) && J < Sh::OFF(b + 1)) {
+        const int c = J - Sh::OFF(b);
+        const int j3 = c / (R1b * R2b), r = c % (R1b * R2b);
+        column<S, P, Real, b>(s_F, s_C, J, r % R1b, r / R1b, j3, col, lane);
+      }
+    });
+  }
   if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
 }
 
