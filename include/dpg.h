@@ -149,9 +149,12 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
                                const dpg_opts* opts, void* stream);
 
 /* Autotuning of the work decomposition (column slabs per workgroup, the
- * kernels' tile shape along the packed output).  dpg_autotune times every
- * candidate on the given elements (writing their Gram matrices to out, like
- * dpg_gram_integrate), records the fastest for (space, p, precision, path)
+ * kernels' tile shape along the packed output; on the general path also the
+ * schedule of the diagonal (i3 = j3) pairs: after all others with a
+ * triangular tile, or each right after its slab's other pairs with a full
+ * tile).  Every schedule gives the same result bit for bit.  dpg_autotune
+ * times every candidate on the given elements (writing their Gram matrices to
+ * out, like dpg_gram_integrate), records the fastest for (space, p, precision, path)
  * at the batch-size class floor(log2(n_elem)) in the context, and returns it
  * in *slab_group (optional).  Blocking: synchronises stream.  Later
  * dpg_gram_integrate / _batched calls use the table entry of the nearest size

@@ -57,7 +57,7 @@ int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const 
 
 int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
-                    int slab_group, hipStream_t st) {
+                    Sched sched, hipStream_t st) {
   const int L = npoints(space, p);
   if (o.nq != 0 && o.nq != L)
     return fail(DPG_EINVAL, "nq=%d: only the default point count (%d) is built", o.nq, L);
@@ -76,7 +76,8 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
   a.elem_ids = elem_ids;
   a.n_items = n_items;
   a.out_offset = out_offset;
-  a.slab_group = slab_group;
+  a.slab_group = sched.slab_group;
+  a.diag_inline = sched.diag;
   const hipError_t e = use_reduced(geom, o) ? launch_affine(space, p, o.prec, a, st)
                                             : launch_general(space, p, o.prec, a, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -201,7 +202,7 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
   if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
   if (geom->n_elem == 0) return DPG_OK;
   const bool red = dpg::use_reduced(geom, o);
-  const int g = dpg::tuned_slab_group(ctx, space, p, o.prec, red, geom->n_elem);
+  const dpg::Sched g = dpg::tuned_sched(ctx, space, p, o.prec, red, geom->n_elem);
   return dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, geom->n_elem, nullptr, g,
                               static_cast<hipStream_t>(stream));
 }

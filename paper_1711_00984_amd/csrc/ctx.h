@@ -18,7 +18,8 @@ int hip_fail(hipError_t e, const char* what);
 inline bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
 
 // Autotuning key: one (space, order, precision, path) at a batch-size class
-// (floor(log2(n_elem))).  Value: column slabs per workgroup and its time.
+// (floor(log2(n_elem))).  Value: the schedule (column slabs per workgroup and
+// the diagonal-pair schedule) and its time.
 struct TuneKey {
   int space, p, prec, reduced, size_class;
   bool operator<(const TuneKey& o) const {
@@ -32,6 +33,15 @@ struct TuneKey {
 struct TuneVal {
   int slab_group;
   float ms;
+  int diag = -1;
+};
+
+// Work decomposition of a general-path launch: slabs per workgroup (0 = kernel
+// heuristic) and diagonal pairs (-1 = default for the order, 0 = last with the
+// triangular x tiling, 1 = each closing its slab in the full x tiling).
+struct Sched {
+  int slab_group = 0;
+  int diag = -1;
 };
 
 struct BatchPlan;   // batch.cpp
@@ -63,10 +73,10 @@ int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const 
 // items to elements, nullptr = identity; out_offset nullptr = e * packed_len).
 int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
-                    int slab_group, hipStream_t st);
+                    Sched sched, hipStream_t st);
 
-// Slabs per workgroup from the tuning table (0 = not tuned: kernel heuristic).
-int tuned_slab_group(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n);
+// Schedule from the tuning table (defaults when not tuned).
+Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n);
 
 void destroy_plans(dpg_ctx* ctx);
 

@@ -91,6 +91,9 @@ constexpr int NTHREADS = 256;
 #ifndef DPG_C2_MAX
 #define DPG_C2_MAX 24
 #endif
+#ifndef DPG_PIPE
+#define DPG_PIPE 0
+#endif
 #ifndef DPG_YB
 #define DPG_YB 4
 #endif
@@ -295,6 +298,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(Real* p, long long n)
   return __builtin_amdgcn_make_buffer_rsrc(p, 0, int(n * (long long)sizeof(Real)), 0x00020000);
 }
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+// Byte offset that lands past any element's packed range (at most 2^28 bytes), used
+// for lanes that hold padding; sums of two such offsets and a real one stay below 2^31.
+constexpr unsigned kDropOff = 1u << 29;
 __device__ __forceinline__ void store_out(double v, __amdgpu_buffer_rsrc_t r, int off) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
@@ -308,12 +314,18 @@ __device__ __forceinline__ void store_out(float v, __amdgpu_buffer_rsrc_t r, int
 // (j3, j3) of a diagonal block.  A batch is a run [t0, t0 + np) of one list.
 // ---------------------------------------------------------------------------
 template <int S, int P, int A, int B>
-__device__ __forceinline__ void pair_of(bool diag, int t, int lo, int& i3, int& j3) {
+__device__ __forceinline__ void pair_of(bool diag, int t, int lo, bool inl, int& i3, int& j3) {
   using BC = Blk<S, P, A, B>;
   if (diag) { i3 = lo + t; j3 = lo + t; return; }
   if constexpr (A != B) {
     j3 = lo + t / BC::R3a;
     i3 = t % BC::R3a;
+  } else if (inl) {
+    // i3 = 0 .. j3 inclusive: the diagonal pair closes its slab
+    int j = lo;
+    while (t > j) { t -= j + 1; ++j; }
+    j3 = j;
+    i3 = t;
   } else {
     int j = lo;
     while (t >= j) { t -= j; ++j; }
@@ -369,7 +381,8 @@ template <int S, int P, typename Real, int A, int B> struct S3Roles {
     for (int q = 0; q < QS; ++q) m = imax(m, nfs(q));
     return m;
   }();
-  static constexpr bool REGF = ROUNDS == 1 && NFS * L <= DPG_REGF_MAX;   // field column fits in registers
+  // field column fits in registers (not with line writes, whose staging needs the registers)
+  static constexpr bool REGF = ROUNDS == 1 && NFS * L <= DPG_REGF_MAX;
 };
 
 // Stage-2 table operands of a wave's fixed x-tile kept in registers: when a
@@ -400,7 +413,7 @@ template <int S, int P, typename Real, int A, int B> struct Regs {
 // stage 3: A[pg][(q, m)][row(pi, l)] = sum_n c(l, m, n) T_i3(n) T_j3(n) for the batch's pairs
 template <int S, int P, typename Real, int A, int B>
 __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, bool diag, int t0,
-                                       int np, int lo, Real* sAb) {
+                                       int np, int lo, bool inl, Real* sAb) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
   using CF = Cfg<S, P, Real>;
@@ -417,7 +430,7 @@ __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real
     const int l = idx % L, m = (idx / L) % L, k = idx / L2;
     if (k >= np) continue;
     int i3, j3;
-    pair_of<S, P, A, B>(diag, t0 + k, lo, i3, j3);
+    pair_of<S, P, A, B>(diag, t0 + k, lo, inl, i3, j3);
     const int pg = k / BC::NP, pi = k % BC::NP;
     const int ka = i3 + Sh::SH(A, 2), kb = j3 + Sh::SH(B, 2);
     Real* dst = sAb + pg * CF::AONE + m * 16 + M::crow(l & 3, pi * BC::RPP + (l >> 2));
@@ -452,10 +465,9 @@ __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real
   }
 }
 
-// stages 2 and 1 and the packed store for the work items of this wave in one batch
 template <int S, int P, typename Real, int A, int B, bool DIAG>
 __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, int t0, int np, int lo,
-                                     const Real* sAb, Real* __restrict__ outp) {
+                                     bool inl, const Real* sAb, Real* __restrict__ outp) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
   using CF = Cfg<S, P, Real>;
@@ -470,6 +482,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  static_assert(gram_dim(S, P) < (1 << 13) && packed_len(S, P) * 8 < (1ll << 28), "store offset bounds");
   const __amdgpu_buffer_rsrc_t rsrc = out_rsrc(outp, packed_len(S, P));
   for (int item = wave; item < CF::NB * XT; item += 4) {
     const int pg = item / XT, xt = item % XT;
@@ -501,76 +514,121 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
       });
     });
     // ---------------- stage 1 and store ----------------
-    // x of this lane's accumulator register r: xt * 16 + lk + 4 r
-    int xi2[4], xj2[4];
-    bool xv[4];
+    // x of this lane's accumulator register r: xt * 16 + lk + 4 r.  Its share of the
+    // packed offset, pair-independent: the row part R1a i2 in bytes (past the element's
+    // range when x is padding, so such stores drop) and the column part R1b j2.
+    unsigned xa8[4], xb[4];
+    bool xlt[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int s = xt * 16 + lk + 4 * r;
-      xv[r] = s < NXv;
-      xi2[r] = 0;
-      xj2[r] = 0;
-      if (xv[r]) decode_x<BC::R2a, DIAG>(sm.xd, s, xi2[r], xj2[r]);
+      int i2 = 0, j2 = 0;
+      if (s < NXv) decode_x<BC::R2a, DIAG>(sm.xd, s, i2, j2);
+      xa8[r] = s < NXv ? unsigned(BC::R1a * i2 * int(sizeof(Real))) : kDropOff;
+      xb[r] = unsigned(BC::R1b * j2);
+      xlt[r] = i2 < j2;
     }
+    // the pairs' uniform row and column bases
+    int Ibp[NP], Jbp[NP];
+    bool dgp[NP];   // a diagonal pair in the full x tiling: its lower triangle is dropped
     static_for<NP>([&](auto PI) {
       constexpr int pi = decltype(PI)::value;
-      if (pi >= npg) return;
-      int i3, j3;
-      pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, i3, j3);
-      const int Ib = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
-      const int Jb = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
-      static_for<YCH>([&](auto YC) {
-        constexpr int yc = decltype(YC)::value;
-        typename M::acc acc1[YB];
+      int i3 = 0, j3 = 0;
+      if (pi < npg) pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, inl, i3, j3);
+      Ibp[pi] = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
+      Jbp[pi] = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
+      dgp[pi] = A == B && !DIAG && i3 == j3;
+    });
+    using Acc = typename M::acc;
+    // stage 1 of step (pair pi, y chunk yc) into acc1
+    auto mm = [&](auto PI, auto YC, Acc (&acc1)[YB]) {
+      constexpr int pi = decltype(PI)::value, yc = decltype(YC)::value;
 #pragma unroll
-        for (int c = 0; c < YB; ++c) acc1[c] = typename M::acc{0, 0, 0, 0};
-        static_for<BC::NG>([&](auto G) {
-          constexpr int g = decltype(G)::value;
-          constexpr int r1 = BC::PL.gr1[g], s1 = BC::PL.gs1[g];
-          static_for<RPP>([&](auto RHO) {
-            constexpr int rho = decltype(RHO)::value;
-            const Real a = acc2[g][pi * RPP + rho];
-            static_for<YB>([&](auto YY) {
-              constexpr int yt = yc * YB + decltype(YY)::value;
-              if constexpr (yt < BC::NYT) {
-                Real u;
-                if constexpr (Cache1<S, P, A, B>::ON) {
-                  u = rg.u1[(g * RPP + rho) * BC::NYT + yt];
-                } else if constexpr (CF::U1TAB) {
-                  u = sU1[((g * RPP + rho) * BC::NYT + yt) * 64 + lane];
-                } else {
-                  const int y = yt * 16 + lr;
-                  const int yy = y < BC::NY ? y : 0;
-                  const int i1 = yy % BC::R1a, j1 = yy / BC::R1a;
-                  u = sT[r1 * KTL + (i1 + Sh::SH(A, 0)) * L + lk + 4 * rho] *
-                      sT[s1 * KTL + (j1 + Sh::SH(B, 0)) * L + lk + 4 * rho];
-                }
-                acc1[decltype(YY)::value] = M::mac(a, u, acc1[decltype(YY)::value]);
+      for (int c = 0; c < YB; ++c) acc1[c] = Acc{0, 0, 0, 0};
+      static_for<BC::NG>([&](auto G) {
+        constexpr int g = decltype(G)::value;
+        constexpr int r1 = BC::PL.gr1[g], s1 = BC::PL.gs1[g];
+        static_for<RPP>([&](auto RHO) {
+          constexpr int rho = decltype(RHO)::value;
+          const Real a = acc2[g][pi * RPP + rho];
+          static_for<YB>([&](auto YY) {
+            constexpr int yt = yc * YB + decltype(YY)::value;
+            if constexpr (yt < BC::NYT) {
+              Real u;
+              if constexpr (Cache1<S, P, A, B>::ON) {
+                u = rg.u1[(g * RPP + rho) * BC::NYT + yt];
+              } else if constexpr (CF::U1TAB) {
+                u = sU1[((g * RPP + rho) * BC::NYT + yt) * 64 + lane];
+              } else {
+                const int y = yt * 16 + lr;
+                const int yy = y < BC::NY ? y : 0;
+                const int i1 = yy % BC::R1a, j1 = yy / BC::R1a;
+                u = sT[r1 * KTL + (i1 + Sh::SH(A, 0)) * L + lk + 4 * rho] *
+                    sT[s1 * KTL + (j1 + Sh::SH(B, 0)) * L + lk + 4 * rho];
               }
-            });
+              acc1[decltype(YY)::value] = M::mac(a, u, acc1[decltype(YY)::value]);
+            }
           });
         });
-        // packed store: register r of lane (lk, lr) holds G[x = xt*16 + lk + 4r][y = yt*16 + lr].
-        // Buffer stores without branches: a lane with nothing to store gets an
-        // offset past the element's range, which the buffer unit discards.
-        static_for<YB>([&](auto YY) {
-          constexpr int yt = yc * YB + decltype(YY)::value;
-          if constexpr (yt < BC::NYT) {
-            const int y = yt * 16 + lr;
-            const bool yv = y < BC::NY;
-            const int i1 = y % BC::R1a, j1 = y / BC::R1a;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const bool ok = yv && xv[r] && (!DIAG || xi2[r] < xj2[r] || i1 <= j1);
-              const unsigned I = unsigned(Ib + i1 + BC::R1a * xi2[r]);
-              const unsigned J = unsigned(Jb + j1 + BC::R1b * xj2[r]);
-              const int off = ok ? int((I + ((J * (J + 1)) >> 1)) * sizeof(Real)) : 0x7fffffff;
-              store_out(acc1[decltype(YY)::value][r], rsrc, off);
-            }
-          }
-        });
       });
-    });
+    };
+    // packed store of step (pi, yc): register r of lane (lk, lr) holds G[x = xt*16 + lk + 4r]
+    // [y = yt*16 + lr], entry I + J(J+1)/2 of the packed column J.  Buffer stores without
+    // branches: a lane with nothing to store gets an offset past the element's range, which
+    // the buffer unit discards.  J < 2^13, so J(J+1) is one 24-bit multiply-add.
+    auto st = [&](auto PI, auto YC, const Acc (&acc1)[YB]) {
+      constexpr int pi = decltype(PI)::value, yc = decltype(YC)::value;
+      const int Ib = Ibp[pi], Jb = Jbp[pi];
+      static_for<YB>([&](auto YY) {
+        constexpr int yt = yc * YB + decltype(YY)::value;
+        if constexpr (yt < BC::NYT) {
+          const int y = yt * 16 + lr;
+          const int i1 = y % BC::R1a, j1 = y / BC::R1a;
+          const unsigned ya8 = y < BC::NY ? unsigned((Ib + i1) * int(sizeof(Real))) : kDropOff;
+          const unsigned yb = unsigned(Jb + j1);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const unsigned J = yb + xb[r];
+            const unsigned JJ = __umul24(J, J) + J;
+            unsigned off = (JJ << (sizeof(Real) == 8 ? 2 : 1)) + ya8 + xa8[r];
+            if constexpr (DIAG) off = (xlt[r] || i1 <= j1) ? off : kDropOff;
+            if constexpr (A == B && !DIAG && diag_inline_ok(S, P)) {
+              const unsigned il = unsigned(i1 * int(sizeof(Real))) + xa8[r];
+              const unsigned jl = (unsigned(j1) + xb[r]) * unsigned(sizeof(Real));
+              off = (dgp[pi] && il > jl) ? kDropOff : off;
+            }
+            store_out(acc1[decltype(YY)::value][r], rsrc, int(off));
+          }
+        }
+      });
+    };
+    // steps (pi, yc) in order; with DPG_PIPE the MFMAs of the next step are issued before the
+    // stores of the current one, so the stores wait on finished accumulators only
+    constexpr int NSTEP = NP * YCH;
+    if constexpr (DPG_PIPE) {
+      Acc ping[YB], pong[YB];
+      mm(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, ping);
+      static_for<NSTEP>([&](auto STEP) {
+        constexpr int sp = decltype(STEP)::value, nx = sp + 1;
+        if constexpr (nx < NSTEP) {
+          if (nx / YCH < npg)
+            mm(std::integral_constant<int, nx / YCH>{}, std::integral_constant<int, nx % YCH>{},
+               (nx & 1) ? pong : ping);
+        }
+        if (sp / YCH < npg)
+          st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{},
+             (sp & 1) ? pong : ping);
+      });
+    } else {
+      static_for<NSTEP>([&](auto STEP) {
+        constexpr int sp = decltype(STEP)::value;
+        if (sp / YCH < npg) {
+          Acc acc1[YB];
+          mm(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
+          st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
+        }
+      });
+    }
   }
 }
 
@@ -687,8 +745,13 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   // ABUF == 2: [stage 3 (b+1) | stages 2+1 (b)] barrier ...
   // ABUF == 1: [stages 2+1 (b)] barrier [stage 3 (b+1)] barrier ...
   constexpr int NBP = CF::NBP;
-  const int n_nd = A != B ? BC::R3a * (j3_hi - j3_lo) : (j3_hi * (j3_hi - 1) - j3_lo * (j3_lo - 1)) / 2;
-  const int n_d = A == B ? j3_hi - j3_lo : 0;
+  // diagonal pairs either close their slab in the full x tiling (inl) or come last, in
+  // batches of their own with the triangular x tiling
+  const bool inl = diag_inline_ok(S, P) && ga.diag_inline != 0;
+  const int n_nd = A != B ? BC::R3a * (j3_hi - j3_lo)
+                 : inl ? (j3_hi * (j3_hi + 1) - j3_lo * (j3_lo + 1)) / 2
+                       : (j3_hi * (j3_hi - 1) - j3_lo * (j3_lo - 1)) / 2;
+  const int n_d = A == B && !inl ? j3_hi - j3_lo : 0;
   const int nb_nd = (n_nd + NBP - 1) / NBP;
   const int nbt = nb_nd + (n_d + NBP - 1) / NBP;
   auto batch = [&](int b, bool& dg, int& t0, int& np) {
@@ -700,7 +763,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   if (nbt > 0) {
     bool dg; int t0, np;
     batch(0, dg, t0, np);
-    stage3<S, P, Real, A, B>(sm, rg, dg, t0, np, j3_lo, sA);
+    stage3<S, P, Real, A, B>(sm, rg, dg, t0, np, j3_lo, inl, sA);
   }
   __syncthreads();
   for (int b = 0; b < nbt; ++b) {
@@ -711,17 +774,17 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       if (b + 1 < nbt) {
         bool dn; int tn, nn;
         batch(b + 1, dn, tn, nn);
-        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, sA + ((b + 1) & 1) * ASTRIDE);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA + ((b + 1) & 1) * ASTRIDE);
       }
     }
-    if (dg) work<S, P, Real, A, B, true>(sm, rg, t0, np, j3_lo, cur, outp);
-    else work<S, P, Real, A, B, false>(sm, rg, t0, np, j3_lo, cur, outp);
+    if (dg) work<S, P, Real, A, B, true>(sm, rg, t0, np, j3_lo, inl, cur, outp);
+    else work<S, P, Real, A, B, false>(sm, rg, t0, np, j3_lo, inl, cur, outp);
     __syncthreads();
     if constexpr (CF::ABUF == 1) {
       if (b + 1 < nbt) {
         bool dn; int tn, nn;
         batch(b + 1, dn, tn, nn);
-        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, sA);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA);
         __syncthreads();
       }
     }
@@ -824,6 +887,7 @@ hipError_t launch_general_one(const GeneralArgs& a, hipStream_t st) {
   constexpr int NS = Shape<S, P>::NSLAB;
   GeneralArgs c = a;
   c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
+  if (c.diag_inline < 0 || !diag_inline_ok(S, P)) c.diag_inline = diag_inline_ok(S, P) ? 1 : 0;
   const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
   const int64_t max_items = int64_t(0x7fffffff) / ngroups;
   for (int64_t base = 0; base < a.n_items; base += max_items) {

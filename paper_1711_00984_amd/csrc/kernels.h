@@ -37,6 +37,8 @@ struct GeneralArgs {
   double w0, w1;
   int32_t* status;           // per element (nullptr: none)
   int slab_group;            // column slabs per workgroup (0: choose from the batch size)
+  int diag_inline;           // diagonal pairs: -1 default for the order, 0 last with the
+                             // triangular x tiling, 1 each closing its slab (full x tiling)
 };
 
 // Column slabs per workgroup: whole elements when the batch alone fills the GPU

@@ -73,6 +73,11 @@ constexpr int shift1d(int space, int a, int d) {
 }
 
 constexpr int npoints(int space, int p) { return space == SP_L2 ? p : p + 1; }
+// Diagonal (i3 = j3) pairs closing their slab in the full x tiling, lower triangle
+// dropped, are built where a stage-2 row tile holds two or more pairs (L <= 8
+// points), so the diagonal pair shares its tile; with one pair per tile the
+// triangular x tiling of a separate diagonal pass is cheaper.
+constexpr bool diag_inline_ok(int space, int p) { return npoints(space, p) <= 8; }
 
 struct Term {
   int field;

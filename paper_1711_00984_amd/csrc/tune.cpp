@@ -1,9 +1,14 @@
 // tune.cpp -- autotuner for the work decomposition of the integration kernels.
 //
-// The tunable is the number of column slabs one workgroup integrates (1 ..
-// all slabs of an element).  More slabs per workgroup amortise the metric
-// evaluation and the per-block table registers over more pairs; fewer give
-// more, smaller workgroups (load balance, occupancy of the tail).  The best
+// The tunables are the number of column slabs one workgroup integrates (1 ..
+// all slabs of an element) and, on the general path, where the diagonal
+// (i3 = j3) pairs of the diagonal blocks go.  More slabs per workgroup
+// amortise the metric evaluation and the per-block table registers over more
+// pairs; fewer give more, smaller workgroups (load balance, occupancy of the
+// tail).  A diagonal pair that closes its slab in the full x tiling costs
+// extra MFMA work on its lower triangle but writes the line it shares with
+// the slab's last off-diagonal segment right after it, so the L2 merges the
+// two halves instead of writing them back to HBM separately.  The best
 // choice depends on (space, p, precision, path) and on the batch size, so
 // the tuner times the candidates on the caller's data and records the
 // winner per batch-size class (floor(log2(n_elem))).  The table can be saved
@@ -28,16 +33,17 @@ static int nslab(int space, int p) {
   return o;
 }
 
-int tuned_slab_group(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n) {
+Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n) {
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (ctx->tune.empty()) return 0;
+  dpg::Sched best;
+  if (ctx->tune.empty()) return best;
   const int sc = size_class(n);
-  int best = 0, bestd = 3;
+  int bestd = 3;
   for (const auto& kv : ctx->tune) {
     const TuneKey& k = kv.first;
     if (k.space != space || k.p != p || k.prec != prec || k.reduced != int(reduced)) continue;
     const int d = std::abs(k.size_class - sc);
-    if (d < bestd) { bestd = d; best = kv.second.slab_group; }
+    if (d < bestd) { bestd = d; best = Sched{kv.second.slab_group, kv.second.diag}; }
   }
   return best;
 }
@@ -75,14 +81,17 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
   const bool red = dpg::use_reduced(geom, o);
-  int best = 0;
+  std::vector<int> diags = {-1};
+  if (!red) diags = dpg::diag_inline_ok(space, p) ? std::vector<int>{0, 1} : std::vector<int>{0};
+  dpg::Sched best;
   float best_ms = 1e30f;
-  for (int g : cand) {
+  for (int g : cand)
+  for (int dg : diags) {
     float t = 1e30f;
     for (int rep = 0; rep < 4 && rc == DPG_OK; ++rep) {
       he = hipEventRecord(e0, st);
       if (he != hipSuccess) { rc = hip_fail(he, "hipEventRecord"); break; }
-      rc = dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, n, nullptr, g, st);
+      rc = dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, n, nullptr, dpg::Sched{g, dg}, st);
       if (rc) break;
       he = hipEventRecord(e1, st);
       if (he == hipSuccess) he = hipEventSynchronize(e1);
@@ -92,16 +101,16 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
       if (rep > 0) t = std::min(t, ms);   // the first run warms up
     }
     if (rc) break;
-    if (t < best_ms) { best_ms = t; best = g; }
+    if (t < best_ms) { best_ms = t; best = dpg::Sched{g, dg}; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->tune[dpg::TuneKey{space, p, o.prec, int(red), dpg::size_class(n)}] = dpg::TuneVal{best, best_ms};
+    ctx->tune[dpg::TuneKey{space, p, o.prec, int(red), dpg::size_class(n)}] = dpg::TuneVal{best.slab_group, best_ms, best.diag};
   }
-  if (slab_group) *slab_group = best;
+  if (slab_group) *slab_group = best.slab_group;
   return DPG_OK;
 }
 
@@ -112,12 +121,12 @@ int dpg_tune_save(const dpg_ctx* ctx, const char* path) {
   if (!f) return fail(DPG_EINVAL, "cannot write %s", path);
   std::lock_guard<std::mutex> lk(ctx->mu);
   std::fprintf(f, "{\"arch\": \"gfx950\", \"fields\": [\"space\", \"p\", \"prec\", \"reduced\", \"size_class\", "
-                  "\"slab_group\", \"ms\"],\n \"tune\": [");
+                  "\"slab_group\", \"ms\", \"diag\"],\n \"tune\": [");
   bool first = true;
   for (const auto& kv : ctx->tune) {
     const auto& k = kv.first;
-    std::fprintf(f, "%s\n  [%d, %d, %d, %d, %d, %d, %.6g]", first ? "" : ",", k.space, k.p, k.prec, k.reduced,
-                 k.size_class, kv.second.slab_group, double(kv.second.ms));
+    std::fprintf(f, "%s\n  [%d, %d, %d, %d, %d, %d, %.6g, %d]", first ? "" : ",", k.space, k.p, k.prec, k.reduced,
+                 k.size_class, kv.second.slab_group, double(kv.second.ms), kv.second.diag);
     first = false;
   }
   std::fprintf(f, "\n ]}\n");
@@ -146,14 +155,15 @@ int dpg_tune_load(dpg_ctx* ctx, const char* path) {
     const size_t a = s.find('[', pos);
     const size_t close = s.find(']', pos);
     if (a == std::string::npos || (close != std::string::npos && close < a)) break;
-    int v[6];
+    int v[6], diag = -1;
     double ms;
-    if (std::sscanf(s.c_str() + a + 1, " %d , %d , %d , %d , %d , %d , %lf", &v[0], &v[1], &v[2], &v[3], &v[4],
-                    &v[5], &ms) != 7)
-      return fail(DPG_EINVAL, "%s: malformed row", path);
-    if (!dpg::valid_space(v[0]) || v[1] < 1 || v[1] > DPG_P_MAX || v[5] < 1)
+    // rows without the diagonal schedule (older tables) keep its default
+    const int got = std::sscanf(s.c_str() + a + 1, " %d , %d , %d , %d , %d , %d , %lf , %d", &v[0], &v[1], &v[2],
+                                &v[3], &v[4], &v[5], &ms, &diag);
+    if (got != 7 && got != 8) return fail(DPG_EINVAL, "%s: malformed row", path);
+    if (!dpg::valid_space(v[0]) || v[1] < 1 || v[1] > DPG_P_MAX || v[5] < 1 || diag < -1 || diag > 1)
       return fail(DPG_EINVAL, "%s: invalid row", path);
-    rows.push_back({dpg::TuneKey{v[0], v[1], v[2], v[3], v[4]}, dpg::TuneVal{v[5], float(ms)}});
+    rows.push_back({dpg::TuneKey{v[0], v[1], v[2], v[3], v[4]}, dpg::TuneVal{v[5], float(ms), diag}});
     pos = s.find(']', a);
     if (pos == std::string::npos) break;
     ++pos;
@@ -165,7 +175,7 @@ int dpg_tune_load(dpg_ctx* ctx, const char* path) {
 
 int dpg_tune_lookup(const dpg_ctx* ctx, int space, int p, int prec, int reduced, int64_t n_elem) {
   if (!ctx || !dpg::valid_space(space)) return -1;
-  return dpg::tuned_slab_group(ctx, space, p, prec, reduced != 0, n_elem);
+  return dpg::tuned_sched(ctx, space, p, prec, reduced != 0, n_elem).slab_group;
 }
 
 }  // extern "C"

@@ -319,3 +319,57 @@ def test_batched_graph_replays(ctx, dpg):
     single = ctx.gram(int(space[0]), int(pr2[0]), X_d[0:1])
     torch.cuda.synchronize()
     assert torch.equal(out2[:lens2[0]], single)
+
+
+def _force_schedule(ctx, tmp_path, space, p, prec, n, G, diag):
+    """Pin the work decomposition through the tuning table (a JSON row):
+    G slabs per workgroup, diagonal pairs last (0) or closing their slab (1)."""
+    import json
+    sid = {"H1": 0, "HCURL": 1, "HDIV": 2, "L2": 3}[space]
+    f = tmp_path / f"force_{space}_{p}_{prec}_{G}_{diag}.json"
+    f.write_text(json.dumps({"arch": "gfx950", "fields": [], "tune": [
+        [sid, p, 0 if prec == "fp64" else 1, 0, int(np.floor(np.log2(n))), G, 1.0, diag]]}))
+    ctx.tune_load(f)
+
+
+@pytest.mark.parametrize("space,p", [("H1", 7), ("L2", 8), ("HCURL", 4), ("H1", 9)])
+def test_every_schedule_agrees(ctx, dpg, tmp_path, space, p):
+    """Slab groups move the workgroup boundaries; the diagonal schedule moves the
+    diagonal pairs between their own triangular-tile batches and the end of each
+    slab (full tile, lower triangle dropped).  Every combination must give the same
+    output bit for bit, and the oracle within the FP64 / FP32 tolerances (p <= 7).
+    Covers two pairs per row tile (H1 7), one (L2 8, H1 9) and several blocks."""
+    say(f"schedules {space} p={p}")
+    n = 5
+    X = meshgen.perturbed_hexes(n, seed=81)
+    ns = sum(r[2] for r in shapes.ranges(space, p))
+    ref = {e: og.gram(space, p, "trilinear", X[e]) for e in (0, n - 1)} if p <= 7 else {}
+    for prec in ("fp64", "fp32"):
+        outs = []
+        for G in sorted({1, 2, 3, ns}):
+            for diag in (0, 1):
+                _force_schedule(ctx, tmp_path, space, p, prec, n, G, diag)
+                assert ctx.tune_lookup(space, p, prec=prec, n_elem=n) == G
+                outs.append(run(ctx, space, p, X, prec=prec).cpu().numpy())
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0]), f"{space} p={p} {prec}: schedules disagree"
+        for e, R in ref.items():
+            G_ = elem(outs[0], e, space, p)
+            if prec == "fp64":
+                compare64(G_, R, f"{space} p={p} element {e}")
+            else:
+                fro = np.linalg.norm(G_ - R) / np.linalg.norm(R)
+                assert fro <= FP32_REL, f"{space} p={p} fp32 element {e}: {fro:.3e}"
+
+
+def test_tune_table_rows(ctx, dpg, tmp_path):
+    """Tables written before the diagonal schedule existed (7 fields) still load;
+    a diagonal schedule outside {-1, 0, 1} is rejected."""
+    import json
+    f = tmp_path / "old.json"
+    f.write_text(json.dumps({"arch": "gfx950", "fields": [], "tune": [[0, 4, 0, 0, 3, 2, 1.0]]}))
+    ctx.tune_load(f)
+    assert ctx.tune_lookup("H1", 4, n_elem=8) == 2
+    f.write_text(json.dumps({"arch": "gfx950", "fields": [], "tune": [[0, 4, 0, 0, 3, 2, 1.0, 5]]}))
+    with pytest.raises(dpg.DpgError):
+        ctx.tune_load(f)
