@@ -91,6 +91,9 @@ constexpr int NTHREADS = 256;
 #ifndef DPG_C2_MAX
 #define DPG_C2_MAX 24
 #endif
+#ifndef DPG_HOLD_HEADS
+#define DPG_HOLD_HEADS 1
+#endif
 #ifndef DPG_PIPE
 #define DPG_PIPE 0
 #endif
@@ -173,8 +176,16 @@ template <int S, int P, typename Real> struct Cfg {
   static constexpr int U1_LEN = NG * RPP * NYT * 64;
   static constexpr int SMALL = 8 * (2 * L + 24) + 2 * 80 + 64;
   static constexpr int BUDGET = 160 * 1024;
+  // Column heads held back (one block of 8 x 8 planes, inline diagonal pairs, one pair
+  // group per batch): the entries of each local column's first cache line, written by
+  // the slab's first pair, wait in LDS until its diagonal pair writes the line's other
+  // part (the tail of the previous column), so both reach the L2 together.
+  static constexpr int LN = 128 / int(sizeof(Real));   // entries per cache line
+  static constexpr bool HD_SHAPE = DPG_HOLD_HEADS && Sh::NC == 1 && Sh::R(0, 0) == 8 && Sh::R(0, 1) == 8 && diag_inline_ok(S, P);
+  static constexpr int HD_LEN = HD_SHAPE ? 64 * LN : 0;
   static constexpr int bytes(int nb, int abuf, int u1) {
-    return int(sizeof(Real)) * (FLD_LEN + abuf * nb * AONE + T_LEN + (u1 ? U1_LEN : 0)) + SMALL;
+    return int(sizeof(Real)) * (FLD_LEN + abuf * nb * AONE + T_LEN + (u1 ? U1_LEN : 0) + (nb == 1 ? HD_LEN : 0)) +
+           SMALL;
   }
   // fraction of wave time doing useful work items, over the blocks' non-diagonal batches
   static constexpr double balance(int nb) {
@@ -206,6 +217,7 @@ template <int S, int P, typename Real> struct Cfg {
   static constexpr int NB = CHOICE / 100, ABUF = (CHOICE / 10) % 10;
   static constexpr bool U1TAB = CHOICE % 10;
   static constexpr int NBP = NB * NP;                    // pairs per batch
+  static constexpr bool HD = HD_SHAPE && NB == 1;        // one work item per wave and x-tile
   static constexpr int BYTES = bytes(NB, ABUF, U1TAB);
 };
 
@@ -214,6 +226,7 @@ struct SmemPtrs {
   void* A;
   void* U1;
   void* T;
+  void* hd;
   double* z;
   double* w;
   double* X;
@@ -483,6 +496,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   static_assert(gram_dim(S, P) < (1 << 13) && packed_len(S, P) * 8 < (1ll << 28), "store offset bounds");
+  static_assert(!CF::HD || (A == 0 && B == 0 && BC::NXT == 4 && CF::NB == 1 && NP == 2 && BC::R1b == 8 &&
+                            BC::R2b == 8 && BC::NY == 64),
+                "held column heads assume one work item per wave and x-tile over whole j2 rows");
   const __amdgpu_buffer_rsrc_t rsrc = out_rsrc(outp, packed_len(S, P));
   for (int item = wave; item < CF::NB * XT; item += 4) {
     const int pg = item / XT, xt = item % XT;
@@ -531,6 +547,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // the pairs' uniform row and column bases
     int Ibp[NP], Jbp[NP];
     bool dgp[NP];   // a diagonal pair in the full x tiling: its lower triangle is dropped
+    bool hdw[NP], hdf[NP];   // column heads: held back in LDS / written out after this pair
     static_for<NP>([&](auto PI) {
       constexpr int pi = decltype(PI)::value;
       int i3 = 0, j3 = 0;
@@ -538,7 +555,16 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
       Ibp[pi] = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
       Jbp[pi] = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
       dgp[pi] = A == B && !DIAG && i3 == j3;
+      hdw[pi] = hdf[pi] = false;
+      if constexpr (CF::HD && !DIAG) {
+        // slab j3 holds its heads back when its first and its diagonal pair fall in different batches
+        const int tb = (j3 * (j3 + 1) - lo * (lo + 1)) / 2;
+        const bool held = inl && pi < npg && tb / CF::NBP != (tb + j3) / CF::NBP;
+        hdw[pi] = held && i3 == 0;
+        hdf[pi] = held && i3 == j3;
+      }
     });
+    Real* sHD = static_cast<Real*>(sm.hd);
     using Acc = typename M::acc;
     // stage 1 of step (pair pi, y chunk yc) into acc1
     auto mm = [&](auto PI, auto YC, Acc (&acc1)[YB]) {
@@ -597,10 +623,39 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
               const unsigned jl = (unsigned(j1) + xb[r]) * unsigned(sizeof(Real));
               off = (dgp[pi] && il > jl) ? kDropOff : off;
             }
+            if constexpr (CF::HD && !DIAG) {
+              if (hdw[pi]) {
+                // rows of the column's first line (i3 = 0, so I = i1 + 8 i2) go to LDS
+                const unsigned h = (CF::LN - ((JJ >> 1) & (CF::LN - 1))) & (CF::LN - 1);
+                const unsigned I8 = ya8 + xa8[r];
+                if (I8 < h * unsigned(sizeof(Real))) {
+                  sHD[(J - unsigned(Jbp[pi])) * CF::LN + I8 / unsigned(sizeof(Real))] = acc1[decltype(YY)::value][r];
+                  off = kDropOff;
+                }
+              }
+            }
             store_out(acc1[decltype(YY)::value][r], rsrc, int(off));
           }
         }
       });
+    };
+    // after a diagonal pair: the held column heads of its slab, for this x-tile's 16 columns
+    // (j2 = 2 xt, 2 xt + 1), which the same wave held back at the slab's first pair
+    auto flush = [&](auto PI) {
+      constexpr int pi = decltype(PI)::value;
+      if constexpr (CF::HD && !DIAG) {
+        if (hdf[pi]) {
+          for (int k = lane; k < 16 * CF::LN; k += 64) {
+            const int col = k / CF::LN, row = k % CF::LN;
+            const int c = (col & 7) + 8 * (2 * xt + (col >> 3));
+            const unsigned J = unsigned(Jbp[pi] + c);
+            const unsigned JJ = __umul24(J, J) + J;
+            const unsigned h = (CF::LN - ((JJ >> 1) & (CF::LN - 1))) & (CF::LN - 1);
+            if (unsigned(row) < h)
+              store_out(sHD[c * CF::LN + row], rsrc, int(((JJ >> 1) + unsigned(row)) * unsigned(sizeof(Real))));
+          }
+        }
+      }
     };
     // steps (pi, yc) in order; with DPG_PIPE the MFMAs of the next step are issued before the
     // stores of the current one, so the stores wait on finished accumulators only
@@ -615,9 +670,11 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
             mm(std::integral_constant<int, nx / YCH>{}, std::integral_constant<int, nx % YCH>{},
                (nx & 1) ? pong : ping);
         }
-        if (sp / YCH < npg)
+        if (sp / YCH < npg) {
           st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{},
              (sp & 1) ? pong : ping);
+          if constexpr (sp % YCH == YCH - 1) flush(std::integral_constant<int, sp / YCH>{});
+        }
       });
     } else {
       static_for<NSTEP>([&](auto STEP) {
@@ -626,6 +683,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
           Acc acc1[YB];
           mm(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
           st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
+          if constexpr (sp % YCH == YCH - 1) flush(std::integral_constant<int, sp / YCH>{});
         }
       });
     }
@@ -809,6 +867,7 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
   __shared__ Real s_A[CF::ABUF * CF::NB * CF::AONE];
   __shared__ Real s_U1[CF::U1TAB ? CF::U1_LEN : 1];
   __shared__ Real s_T[CF::T_LEN];
+  __shared__ Real s_hd[CF::HD ? CF::HD_LEN : 1];
   __shared__ double s_z[L], s_w[L], s_X[24];
   __shared__ unsigned char s_xd[2 * 80];
   __shared__ int s_bad;
@@ -839,7 +898,7 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
   if (tid == 0) s_bad = 0;
   __syncthreads();
 
-  SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_z, s_w, s_X, s_xd, &s_bad};
+  SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_hd, s_z, s_w, s_X, s_xd, &s_bad};
   Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
   // component b owns slabs [slab0(b), slab0(b) + R3(b)); visit the blocks (a, b), a <= b,
   // for the j3 range of every component the slab group touches
