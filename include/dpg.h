@@ -59,7 +59,7 @@ extern "C" {
 
 enum { DPG_H1 = 0, DPG_HCURL = 1, DPG_HDIV = 2, DPG_L2 = 3 };
 enum { DPG_FP64 = 0, DPG_FP32 = 1 };
-enum { DPG_GEOM_TRILINEAR = 0, DPG_GEOM_AFFINE = 1 };
+enum { DPG_GEOM_TRILINEAR = 0, DPG_GEOM_AFFINE = 1, DPG_GEOM_EXTRUDED = 2 };
 enum { DPG_PATH_AUTO = 0, DPG_PATH_GENERAL = 1, DPG_PATH_REDUCED = 2 };
 
 enum {
@@ -84,6 +84,11 @@ typedef struct dpg_server dpg_server;
  *     master corner (v1,v2,v3); x(xi) = sum_v X_v prod_d (v_d ? xi_d : 1 - xi_d).
  *   DPG_GEOM_AFFINE: data[n_elem][12] = x0[3], J[3][3] row-major, J_ij = dx_i/dxi_j
  *     ((2.2)); x(xi) = x0 + J xi.
+ *   DPG_GEOM_EXTRUDED: data[n_elem][10] = x1_0, lambda1, then (x2, x3) of the
+ *     cross-section corners (v2,v3) = (0,0), (1,0), (0,1), (1,1); x1 = x1_0 +
+ *     lambda1 xi1 and (x2, x3) = sum_{v2,v3} q_{v2 v3} (v2 ? xi2 : 1 - xi2)
+ *     (v3 ? xi3 : 1 - xi3): a quadrilateral extruded along x1, the second form of
+ *     (2.89).  It is the trilinear map with X_v = (x1_0 + lambda1 v1, q_{v2 v3}).
  * The map must be a diffeomorphism (Section 2.2): det J > 0. */
 typedef struct {
   int32_t kind;
@@ -92,7 +97,12 @@ typedef struct {
   const double* data;
 } dpg_geometry;
 
-/* Options.  prec: DPG_FP64 / DPG_FP32.  path: DPG_PATH_*.  nq: points per
+/* Options.  prec: DPG_FP64 / DPG_FP32.  path: DPG_PATH_*.  GENERAL integrates
+ * every kind by quadrature in all three directions (the O(p^7) algorithms).
+ * REDUCED (the default for affine and extruded geometry; rejected for
+ * trilinear) is the O(p^6) path of Section 2.8.1: exact 1D integrals F^{rs}
+ * in all directions for affine maps (Algorithm 10), in xi1 with quadrature in
+ * (xi2, xi3) for extruded maps (Algorithm 11).  nq: points per
  * direction, 0 = default (p+1; p for L2); only the default is built.
  * w0, w1: weights of the value and derivative parts.
  * status: optional device int32[n_elem]; written with DPG_OK or DPG_EJACOBIAN
@@ -164,7 +174,9 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
                  void* stream, int* slab_group);
 int dpg_tune_save(const dpg_ctx* ctx, const char* path);
 int dpg_tune_load(dpg_ctx* ctx, const char* path);
-/* Tuned slabs per workgroup for this case, 0 if untuned, -1 on bad arguments. */
+/* Tuned slabs per workgroup for this case (reduced: 0 general path, 1 reduced
+ * path on affine geometry, 2 on extruded geometry), 0 if untuned, -1 on bad
+ * arguments. */
 int dpg_tune_lookup(const dpg_ctx* ctx, int space, int p, int prec, int reduced, int64_t n_elem);
 /* Number of cached batched-dispatch plans (captured graphs) in the context. */
 int dpg_batch_plans(const dpg_ctx* ctx);

@@ -9,6 +9,8 @@ Layouts (float64, C order):
 * trilinear: [E, 8, 3]; vertex v = v1 + 2 v2 + 4 v3 sits at master corner
   (v1, v2, v3).
 * affine:    [E, 12]; x0[3] followed by J[3, 3] row-major, J_ij = dx_i/dxi_j.
+* extruded:  [E, 10]; x1_0, lambda1, then (x2, x3) of the cross-section corners
+  (v2, v3) = (0,0), (1,0), (0,1), (1,1).
 
 The paper measures a single identity-map element and uses no public
 dataset; these recipes stand in for the workloads of the benchmark configs.
@@ -57,6 +59,31 @@ def affine_as_trilinear(affine):
     J = affine[:, 3:].reshape(-1, 3, 3)
     c = unit_corners()
     return x0[:, None, :] + np.einsum("eij,vj->evi", J, c)
+
+
+def extruded_prisms(n_elem, noise=0.15, lam_lo=0.5, lam_hi=2.0, seed=1716):
+    """Quadrilaterals extruded along x1: corners of the unit square plus
+    U(-noise, noise) per coordinate, lambda1 ~ U(lo, hi), x1_0 ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((n_elem, 10))
+    out[:, 0] = rng.uniform(-1.0, 1.0, size=n_elem)
+    out[:, 1] = rng.uniform(lam_lo, lam_hi, size=n_elem)
+    sq = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=np.float64)
+    out[:, 2:] = (sq[None] + rng.uniform(-noise, noise, size=(n_elem, 4, 2))).reshape(n_elem, 8)
+    return out
+
+
+def extruded_as_trilinear(ext):
+    """Vertices of the extruded maps, for feeding the same elements to the
+    trilinear code path: X_v = (x1_0 + lambda1 v1, q_{v2 v3})."""
+    ext = np.asarray(ext, dtype=np.float64).reshape(-1, 10)
+    c = unit_corners()
+    X = np.zeros((ext.shape[0], 8, 3))
+    X[:, :, 0] = ext[:, :1] + ext[:, 1:2] * c[None, :, 0]
+    q = ext[:, 2:].reshape(-1, 4, 2)
+    corner = (c[:, 1] + 2 * c[:, 2]).astype(int)
+    X[:, :, 1:] = q[:, corner, :]
+    return X
 
 
 def mixed_batch(n_elem, p_lo=2, p_hi=9, dp=1, seed=1714, noise=0.15):

@@ -36,21 +36,22 @@ static hipError_t launch_general(int space, int p, int prec, const GeneralArgs& 
   }
 }
 
-bool use_reduced(const dpg_geometry* geom, const dpg_opts& o) {
-  return o.path == DPG_PATH_REDUCED || (o.path == DPG_PATH_AUTO && geom->kind == DPG_GEOM_AFFINE);
+int path_code(const dpg_geometry* geom, const dpg_opts& o) {
+  const bool red = o.path == DPG_PATH_REDUCED || (o.path == DPG_PATH_AUTO && geom->kind != DPG_GEOM_TRILINEAR);
+  return red ? (geom->kind == DPG_GEOM_EXTRUDED ? 2 : 1) : 0;
 }
 
 int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const dpg_opts& o) {
   if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
   if (!geom) return fail(DPG_EINVAL, "geometry is NULL");
-  if (geom->kind != DPG_GEOM_TRILINEAR && geom->kind != DPG_GEOM_AFFINE)
+  if (geom->kind != DPG_GEOM_TRILINEAR && geom->kind != DPG_GEOM_AFFINE && geom->kind != DPG_GEOM_EXTRUDED)
     return fail(DPG_EINVAL, "unknown geometry kind %d", geom->kind);
   if (geom->n_elem < 0) return fail(DPG_EINVAL, "negative element count");
   if (geom->n_elem > 0 && (!geom->data || !out)) return fail(DPG_EINVAL, "geometry data or output is NULL");
   if (o.prec != DPG_FP64 && o.prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", o.prec);
   if (o.path < DPG_PATH_AUTO || o.path > DPG_PATH_REDUCED) return fail(DPG_EINVAL, "unknown path %d", o.path);
-  if (o.path == DPG_PATH_REDUCED && geom->kind != DPG_GEOM_AFFINE)
-    return fail(DPG_EINVAL, "the reduced path needs affine geometry");
+  if (o.path == DPG_PATH_REDUCED && geom->kind == DPG_GEOM_TRILINEAR)
+    return fail(DPG_EINVAL, "the reduced path needs affine or extruded geometry");
   if (!std::isfinite(o.w0) || !std::isfinite(o.w1)) return fail(DPG_EINVAL, "weights must be finite");
   return DPG_OK;
 }
@@ -78,8 +79,10 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
   a.out_offset = out_offset;
   a.slab_group = sched.slab_group;
   a.diag_inline = sched.diag;
-  const hipError_t e = use_reduced(geom, o) ? launch_affine(space, p, o.prec, a, st)
-                                            : launch_general(space, p, o.prec, a, st);
+  const int pc = path_code(geom, o);
+  const hipError_t e = pc == 2 ? launch_extruded(space, p, o.prec, a, st)
+                     : pc == 1 ? launch_affine(space, p, o.prec, a, st)
+                               : launch_general(space, p, o.prec, a, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return DPG_OK;
 }
@@ -201,8 +204,7 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
   if (!dpg::valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
   if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
   if (geom->n_elem == 0) return DPG_OK;
-  const bool red = dpg::use_reduced(geom, o);
-  const dpg::Sched g = dpg::tuned_sched(ctx, space, p, o.prec, red, geom->n_elem);
+  const dpg::Sched g = dpg::tuned_sched(ctx, space, p, o.prec, dpg::path_code(geom, o), geom->n_elem);
   return dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, geom->n_elem, nullptr, g,
                               static_cast<hipStream_t>(stream));
 }

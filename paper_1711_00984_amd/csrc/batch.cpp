@@ -142,7 +142,7 @@ extern "C" int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* spac
       const int b = order[k];
       const int sp = b / (DPG_P_MAX + 1), pp = b % (DPG_P_MAX + 1);
       const int64_t m = cnt[b + 1] - cnt[b];
-      const dpg::Sched g = dpg::tuned_sched(ctx, sp, pp, o.prec, dpg::use_reduced(geom, o), m);
+      const dpg::Sched g = dpg::tuned_sched(ctx, sp, pp, o.prec, dpg::path_code(geom, o), m);
       e = hipStreamBeginCapture(side, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) break;
       rc = dpg::launch_elements(ctx, sp, pp, geom, out, o, q->d_ids + cnt[b], m, out_offset, g, side);

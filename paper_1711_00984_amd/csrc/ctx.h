@@ -17,7 +17,8 @@ namespace dpg {
 int hip_fail(hipError_t e, const char* what);
 inline bool valid_space(int s) { return s >= DPG_H1 && s <= DPG_L2; }
 
-// Autotuning key: one (space, order, precision, path) at a batch-size class
+// Autotuning key: one (space, order, precision, path: 0 general, 1 reduced on
+// affine geometry, 2 reduced on extruded geometry) at a batch-size class
 // (floor(log2(n_elem))).  Value: the schedule (column slabs per workgroup and
 // the diagonal-pair schedule) and its time.
 struct TuneKey {
@@ -66,7 +67,8 @@ struct dpg_ctx {
 
 namespace dpg {
 
-bool use_reduced(const dpg_geometry* geom, const dpg_opts& o);
+// Kernel family of a launch: 0 general, 1 reduced (affine), 2 reduced (extruded).
+int path_code(const dpg_geometry* geom, const dpg_opts& o);
 int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const dpg_opts& o);
 
 // Launch the kernels of one (space, p) over n_items elements (elem_ids maps
@@ -76,7 +78,7 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
                     Sched sched, hipStream_t st);
 
 // Schedule from the tuning table (defaults when not tuned).
-Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n);
+Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int64_t n);
 
 void destroy_plans(dpg_ctx* ctx);
 

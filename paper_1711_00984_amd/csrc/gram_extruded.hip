@@ -1,0 +1,294 @@
+// gram_extruded.hip -- O(p^6) path for extruded elements.
+//
+// Section 2.8.1, second form of (2.89): when x1 = x1_0 + lambda1 xi1 and (x2, x3)
+// depend on (xi2, xi3) only, J, D = J^-1 J^-T and C = J^T J do not depend on xi1,
+// so the xi1 integral of every term is the exact 1D integral F^{r1 s1} (2.90) of
+// the chart, and only xi2, xi3 need quadrature.  Algorithm 11 writes this for L2
+// (nest the xi3 integral inside the xi2 integral, then multiply by the xi1
+// factor); the paper notes the extension to the other spaces, which this kernel
+// implements with the term tables of terms.h.  For block (a, b) and slab j3:
+//
+//   K_g[i3][j2][i2] = sum_{terms t in group g} sign_t w_t
+//                     sum_m T^<r2>_{i2+sa2}(z_m) T^<s2>_{j2+sb2}(z_m)
+//                     sum_n c_t(z_m, z_n) w_m w_n T^<r3>_{i3+sa3}(z_n) T^<s3>_{j3+sb3}(z_n)
+//   G[(i1,i2,i3), (j1,j2,j3)] = sum_g F^{g}_{i1+sa1, j1+sb1} K_g[i3][j2][i2]
+//
+// where a group g collects the terms of one (r1, s1).  The fields c_t come from
+// the full 3 x 3 Jacobian (lambda1 included); the terms whose field couples xi1
+// with xi2 or xi3 vanish on these maps and are dropped (make_ext_plan).
+//
+// Work decomposition: the column slabs of the general path.  Per slab and block
+// (a, b), the workgroup evaluates the fields at the L^2 points (FP64), contracts
+// xi3 then xi2 into K (FP64, stored once in the output precision) in LDS, and the
+// four waves stream the rows of component a of the slab's packed columns, 64
+// consecutive entries per store.  Only F K products remain per output entry, so
+// the kernel is bound by the HBM writes, like the constant-Jacobian path.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "kernels.h"
+#include "metric.h"
+#include "terms.h"
+
+namespace dpg {
+
+namespace {
+
+constexpr int NT_EXT = 256;
+
+template <int S, int P> struct XShape {
+  static constexpr int NC = ncomp(S);
+  static constexpr int L = npoints(S, P);
+  static constexpr int R(int a, int d) { return range1d(S, P, a, d); }
+  static constexpr int SH(int a, int d) { return shift1d(S, a, d); }
+  static constexpr int OFF(int a) { return comp_off(S, P, a); }
+  static constexpr int slab0(int b) {
+    int o = 0;
+    for (int c = 0; c < b; ++c) o += R(c, 2);
+    return o;
+  }
+  static constexpr int NSLAB = slab0(NC);
+  template <typename F> static constexpr int over(F f) {
+    int m = 0;
+    for (int a = 0; a < NC; ++a)
+      for (int b = a; b < NC; ++b) m = f(a, b) > m ? f(a, b) : m;
+    return m;
+  }
+  static constexpr int NF = over([](int a, int b) { return make_ext_plan(S, a, b).nf; });
+  static constexpr int NT = over([](int a, int b) { return make_ext_plan(S, a, b).nt; });
+  static constexpr int NG = over([](int a, int b) { return make_ext_plan(S, a, b).ng; });
+  static constexpr int R3 = over([](int a, int) { return range1d(S, P, a, 2); });
+  static constexpr int K_LEN = over([](int a, int b) {
+    return make_ext_plan(S, a, b).ng * range1d(S, P, a, 2) * range1d(S, P, b, 1) * range1d(S, P, a, 1);
+  });
+};
+
+template <int S, int A, int B> struct XPlan {
+  static constexpr Plan PL = make_ext_plan(S, A, B);
+};
+
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  [&]<int... I>(std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+  }(std::make_integer_sequence<int, N>{});
+}
+
+struct XSmem {
+  const double* T;   // [2][KT][L] FP64 1D tables
+  const double* z;
+  const double* w;
+  const double* X;   // this element's geometry
+  double* fld;       // [NF][L][L] weighted fields of the block
+  double* A;         // [NT][R3][L] xi3 contractions
+  int* bad;
+};
+
+// K of block (a, b) for slab j3 into sK ([g][i3][j2][i2]); sets *bad when |J| <= 0
+// at a quadrature point.
+template <int S, int P, typename Real, int A, int B>
+__device__ __forceinline__ void build_k(const GeneralArgs& ga, const XSmem& sm, int j3, Real* sK) {
+  using Sh = XShape<S, P>;
+  constexpr Plan PL = XPlan<S, A, B>::PL;
+  constexpr int L = Sh::L, L2 = L * L, KTL = KT * L;
+  constexpr int R2a = Sh::R(A, 1), R2b = Sh::R(B, 1), R3a = Sh::R(A, 2);
+  const int tid = threadIdx.x;
+  // weighted coefficient fields at the (xi2, xi3) points, layout [f][m][n]
+  for (int pt = tid; pt < L2; pt += NT_EXT) {
+    const int m = pt / L, n = pt % L;
+    double J[3][3], adj[3][3];
+    jacobian_at(2, sm.X, 0.5, sm.z[m], sm.z[n], J);
+    const double det = adjugate(J, adj);
+    if (!(det > 0.0)) *sm.bad = 1;
+    const double idet = 1.0 / det;
+    const double wq = sm.w[m] * sm.w[n];
+    sfor<PL.nf>([&](auto F) {
+      constexpr int f = decltype(F)::value;
+      constexpr int fid = PL.fid[f];
+      sm.fld[f * L2 + pt] = field_value(fid, J, adj, det, idet) * wq * (field_weight(S, fid) ? ga.w1 : ga.w0);
+    });
+  }
+  __syncthreads();
+  // xi3: A_t[i3][m] = sum_n c_t(m, n) T^<r3>_{i3+sa3}(z_n) T^<s3>_{j3+sb3}(z_n)
+  for (int it = tid; it < PL.nt * R3a * L; it += NT_EXT) {
+    const int m = it % L, i3 = (it / L) % R3a, t = it / (L * R3a);
+    double acc = 0.0;
+    sfor<PL.nt>([&](auto TT) {
+      constexpr int tt = decltype(TT)::value;
+      if (t != tt) return;
+      const double* ti = sm.T + PL.t[tt].r[2] * KTL + (i3 + Sh::SH(A, 2)) * L;
+      const double* tj = sm.T + PL.t[tt].s[2] * KTL + (j3 + Sh::SH(B, 2)) * L;
+      const double* c = sm.fld + PL.tf[tt] * L2 + m * L;
+#pragma unroll
+      for (int n = 0; n < L; ++n) acc += c[n] * ti[n] * tj[n];
+      acc *= double(PL.t[tt].sign);
+    });
+    sm.A[(t * Sh::R3 + i3) * L + m] = acc;
+  }
+  __syncthreads();
+  // xi2: K_g[i3][j2][i2] = sum_{t in g} sum_m A_t[i3][m] T^<r2>_{i2+sa2}(z_m) T^<s2>_{j2+sb2}(z_m)
+  for (int it = tid; it < PL.ng * R3a * R2b * R2a; it += NT_EXT) {
+    const int i2 = it % R2a, j2 = (it / R2a) % R2b, i3 = (it / (R2a * R2b)) % R3a, g = it / (R2a * R2b * R3a);
+    double acc = 0.0;
+    sfor<PL.nt>([&](auto TT) {
+      constexpr int tt = decltype(TT)::value;
+      if (PL.qg[PL.tq[tt]] != g) return;
+      const double* ti = sm.T + PL.t[tt].r[1] * KTL + (i2 + Sh::SH(A, 1)) * L;
+      const double* tj = sm.T + PL.t[tt].s[1] * KTL + (j2 + Sh::SH(B, 1)) * L;
+      const double* a = sm.A + (tt * Sh::R3 + i3) * L;
+#pragma unroll
+      for (int m = 0; m < L; ++m) acc += a[m] * ti[m] * tj[m];
+    });
+    sK[it] = static_cast<Real>(acc);
+  }
+  __syncthreads();
+}
+
+// Rows of component A of the packed columns of slab (B, j3): wave w takes the
+// columns c = w, w + 4, ...; its lanes walk the rows contiguously.
+template <int S, int P, typename Real, int A, int B>
+__device__ __forceinline__ void stream_rows(const Real* sF, const Real* sK, int j3, Real* __restrict__ outp) {
+  using Sh = XShape<S, P>;
+  constexpr Plan PL = XPlan<S, A, B>::PL;
+  constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1), R3a = Sh::R(A, 2);
+  constexpr int R1b = Sh::R(B, 0), R2b = Sh::R(B, 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < R1b * R2b; c += 4) {
+    const int j1 = c % R1b, j2 = c / R1b;
+    const int J = Sh::OFF(B) + R1b * R2b * j3 + c;
+    const int I1 = A < B ? Sh::OFF(A) + R1a * R2a * R3a : J + 1;   // rows [OFF(A), I1)
+    Real* col = outp + int64_t(J) * (J + 1) / 2;
+    const int b1 = j1 + Sh::SH(B, 0);
+    for (int I = Sh::OFF(A) + lane; I < I1; I += 64) {
+      const int loc = I - Sh::OFF(A);
+      const int i1 = loc % R1a, i2 = (loc / R1a) % R2a, i3 = loc / (R1a * R2a);
+      const int a1 = i1 + Sh::SH(A, 0);
+      Real v = Real(0);
+      sfor<PL.ng>([&](auto GG) {
+        constexpr int g = decltype(GG)::value;
+        const Real f = sF[((2 * PL.gr1[g] + PL.gs1[g]) * KT + a1) * KT + b1];
+        v += f * sK[((g * R3a + i3) * R2b + j2) * R2a + i2];
+      });
+      col[I] = v;
+    }
+  }
+}
+
+template <int S, int P, typename Real>
+__global__ void __launch_bounds__(NT_EXT) k_extruded(GeneralArgs ga) {
+  using Sh = XShape<S, P>;
+  constexpr int L = Sh::L;
+  __shared__ Real s_F[FTAB_LEN];
+  __shared__ double s_T[2 * KT * L];
+  __shared__ double s_z[L], s_w[L], s_X[10];
+  __shared__ double s_fld[Sh::NF * L * L];
+  __shared__ double s_A[Sh::NT * Sh::R3 * L];
+  __shared__ Real s_K[Sh::K_LEN];
+  __shared__ int s_bad;
+
+  const int tid = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int G = ga.slab_group;
+  const int ngroups = (Sh::NSLAB + G - 1) / G;
+  const int grp = ngroups - 1 - int(blk / ga.n_items);
+  const int64_t item = ga.item_base + blk % ga.n_items;
+  const int64_t e = ga.elem_ids ? int64_t(ga.elem_ids[item]) : item;
+  const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
+
+  const Real* fR = static_cast<const Real*>(ga.ftabR);
+  for (int i = tid; i < FTAB_LEN; i += NT_EXT) s_F[i] = fR[i];
+  for (int i = tid; i < 2 * KT * L; i += NT_EXT) s_T[i] = ga.tab64[2 * L + i];
+  if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
+  if (tid < 10) s_X[tid] = ga.geom[e * 10 + tid];
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+
+  const XSmem sm{s_T, s_z, s_w, s_X, s_fld, s_A, &s_bad};
+  Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
+  bool bad = false;
+  for (int s = s_lo; s < s_hi && !bad; ++s) {
+    sfor<Sh::NC>([&](auto BB) {
+      constexpr int b = decltype(BB)::value;
+      if (bad || s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) return;
+      const int j3 = s - Sh::slab0(b);
+      sfor<b + 1>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        if (bad) return;
+        build_k<S, P, Real, a, b>(ga, sm, j3, s_K);
+        bad = s_bad != 0;   // uniform: read after the barrier that closes build_k
+        if (!bad) stream_rows<S, P, Real, a, b>(s_F, s_K, j3, outp);
+        __syncthreads();    // s_K and the field buffers are rebuilt for the next block
+      });
+    });
+  }
+  if (bad) {
+    // |J| <= 0 somewhere: the element's output is zero (every slab group clears its columns)
+    const int lane = tid & 63, wave = tid >> 6;
+    sfor<Sh::NC>([&](auto BB) {
+      constexpr int b = decltype(BB)::value;
+      constexpr int w = Sh::R(b, 0) * Sh::R(b, 1);
+      for (int s = s_lo; s < s_hi; ++s) {
+        if (s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) continue;
+        const int J0 = Sh::OFF(b) + (s - Sh::slab0(b)) * w;
+        for (int J = J0 + wave; J < J0 + w; J += 4) {
+          Real* col = outp + int64_t(J) * (J + 1) / 2;
+          for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+        }
+      }
+    });
+  }
+  if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
+}
+
+template <int S, int P, typename Real>
+hipError_t launch_extruded_one(const GeneralArgs& a, hipStream_t st) {
+  constexpr int NS = XShape<S, P>::NSLAB;
+  GeneralArgs c = a;
+  c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
+  const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
+  const int64_t max_items = int64_t(0x7fffffff) / ngroups;
+  for (int64_t base = 0; base < a.n_items; base += max_items) {
+    c.item_base = a.item_base + base;
+    c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
+    hipLaunchKernelGGL((k_extruded<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_EXT), 0, st, c);
+  }
+  return hipGetLastError();
+}
+
+template <int S, typename Real>
+hipError_t extruded_p(int p, const GeneralArgs& a, hipStream_t st) {
+  switch (p) {
+    case 1: return launch_extruded_one<S, 1, Real>(a, st);
+    case 2: return launch_extruded_one<S, 2, Real>(a, st);
+    case 3: return launch_extruded_one<S, 3, Real>(a, st);
+    case 4: return launch_extruded_one<S, 4, Real>(a, st);
+    case 5: return launch_extruded_one<S, 5, Real>(a, st);
+    case 6: return launch_extruded_one<S, 6, Real>(a, st);
+    case 7: return launch_extruded_one<S, 7, Real>(a, st);
+    case 8: return launch_extruded_one<S, 8, Real>(a, st);
+    case 9: return launch_extruded_one<S, 9, Real>(a, st);
+    case 10: return launch_extruded_one<S, 10, Real>(a, st);
+    case 11: return launch_extruded_one<S, 11, Real>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real>
+hipError_t extruded_space(int space, int p, const GeneralArgs& a, hipStream_t st) {
+  switch (space) {
+    case SP_H1: return extruded_p<SP_H1, Real>(p, a, st);
+    case SP_HCURL: return extruded_p<SP_HCURL, Real>(p, a, st);
+    case SP_HDIV: return extruded_p<SP_HDIV, Real>(p, a, st);
+    case SP_L2: return extruded_p<SP_L2, Real>(p, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_extruded(int space, int p, int prec, const GeneralArgs& a, hipStream_t s) {
+  return prec ? extruded_space<float>(space, p, a, s) : extruded_space<double>(space, p, a, s);
+}
+
+}  // namespace dpg

@@ -53,6 +53,7 @@
 #include <utility>
 
 #include "kernels.h"
+#include "metric.h"
 #include "terms.h"
 
 namespace dpg {
@@ -233,67 +234,6 @@ struct SmemPtrs {
   unsigned char* xd;
   int* bad;
 };
-// ---------------------------------------------------------------------------
-// geometry
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void jacobian_at(int kind, const double* X, double x1, double x2, double x3,
-                                            double J[3][3]) {
-  if (kind == 1) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) J[i][j] = X[3 + 3 * i + j];
-    return;
-  }
-  const double a1[2] = {1.0 - x1, x1}, a2[2] = {1.0 - x2, x2}, a3[2] = {1.0 - x3, x3};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        // d/dxi1: edges (0,u,v) -> (1,u,v)
-        c0 += (X[3 * (1 + 2 * u + 4 * v) + i] - X[3 * (2 * u + 4 * v) + i]) * a2[u] * a3[v];
-        // d/dxi2: edges (u,0,v) -> (u,1,v)
-        c1 += (X[3 * (u + 2 + 4 * v) + i] - X[3 * (u + 4 * v) + i]) * a1[u] * a3[v];
-        // d/dxi3: edges (u,v,0) -> (u,v,1)
-        c2 += (X[3 * (u + 2 * v + 4) + i] - X[3 * (u + 2 * v) + i]) * a1[u] * a2[v];
-      }
-    J[i][0] = c0;
-    J[i][1] = c1;
-    J[i][2] = c2;
-  }
-}
-
-// adjugate: J^-1 = adj / det
-__device__ __forceinline__ double adjugate(const double J[3][3], double adj[3][3]) {
-  adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-  adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-  adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-  adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-  adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-  adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-  return J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-}
-
-// metric field value (unweighted) at a point
-__device__ __forceinline__ double field_value(int fid, const double J[3][3], const double adj[3][3],
-                                              double det, double idet) {
-  if (fid == FLD_DETJ) return det;
-  if (fid == FLD_IDETJ) return idet;
-  if (fld_is_D(fid)) {
-    const int s = fid - FLD_D11, a = sym_a(s), b = sym_b(s);
-    return (adj[a][0] * adj[b][0] + adj[a][1] * adj[b][1] + adj[a][2] * adj[b][2]) * idet;
-  }
-  const int s = fid - FLD_C11, a = sym_a(s), b = sym_b(s);
-  return (J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b]) * idet;
-}
-
 // (i2, j2) of x slot s: all pairs (i2 fastest) or the triangle i2 <= j2
 template <int R2a, bool DIAG>
 __device__ __forceinline__ void decode_x(const unsigned char* xd, int s, int& i2, int& j2) {
@@ -886,7 +826,7 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
   // stage-3 output buffers: the padding rows (m >= L) and columns (l >= L) stay zero
   for (int i = tid; i < CF::ABUF * CF::NB * CF::AONE; i += NTHREADS) s_A[i] = Real(0);
   if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
-  const int ng = ga.geom_kind == 1 ? 12 : 24;
+  const int ng = geom_stride(ga.geom_kind);
   if (tid < ng) s_X[tid] = ga.geom[e * ng + tid];
   if (tid < 80) {
     // triangular enumeration s = j2 (j2 + 1) / 2 + i2, i2 <= j2

@@ -24,7 +24,7 @@ constexpr int FTAB_LEN = 4 * KT * KT;   // F^{rs}[i][j] at ((2r+s)*KT + i)*KT + 
 
 struct GeneralArgs {
   const double* geom;        // trilinear [E][8][3] or affine [E][12]
-  int geom_kind;             // 0 trilinear, 1 affine
+  int geom_kind;             // 0 trilinear, 1 affine, 2 extruded
   int64_t n_items;           // elements in this launch
   int64_t item_base;         // first item of this launch (grid chunking)
   const int32_t* elem_ids;   // item -> element (nullptr: identity)
@@ -60,5 +60,9 @@ hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t 
 
 // Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
 hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);
+
+// Reduced path for extruded elements (exact xi1 integrals, quadrature in xi2, xi3);
+// extruded geometry only.
+hipError_t launch_extruded(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);
 
 }  // namespace dpg

@@ -121,7 +121,7 @@ class HipExecutor final : public Executor {
       if (w0.slot0 + w0.n > slots_ || w0.out_off % es) return fail(DPG_EINVAL, "request outside the arenas");
       dpg_geometry g{w0.kind, 0, w0.n, geo + w0.slot0 * gs};
       o.status = status_ + w0.slot0;
-      const Sched G = tuned_sched(ctx_, w0.space, w0.p, w0.prec, use_reduced(&g, o), w0.n);
+      const Sched G = tuned_sched(ctx_, w0.space, w0.p, w0.prec, path_code(&g, o), w0.n);
       rc = launch_elements(ctx_, w0.space, w0.p, &g, out_ + w0.out_off, o, nullptr, w0.n, nullptr, G, st);
     } else {
       // merged: geometry, status and output offsets indexed by slot through the item map
@@ -148,7 +148,7 @@ class HipExecutor final : public Executor {
       if (e != hipSuccess) return hip_fail(e, "item map launch");
       dpg_geometry g{w0.kind, 0, int64_t(slots_), geo};
       o.status = status_;
-      const Sched G = tuned_sched(ctx_, w0.space, w0.p, w0.prec, use_reduced(&g, o), l.items);
+      const Sched G = tuned_sched(ctx_, w0.space, w0.p, w0.prec, path_code(&g, o), l.items);
       rc = launch_elements(ctx_, w0.space, w0.p, &g, out_, o, ids_ + l.ids_off, l.items, off_, G, st);
     }
     if (rc != DPG_OK) return rc;

@@ -108,7 +108,10 @@ constexpr void plan_add(Plan& P, int field, int sign, int r0, int r1, int r2, in
   t.s[0] = s0; t.s[1] = s1; t.s[2] = s2;
 }
 
-constexpr Plan make_plan(int space, int a, int b) {
+constexpr void plan_finish(Plan& P);
+
+// The terms of block (a, b), before grouping.
+constexpr Plan plan_terms(int space, int a, int b) {
   Plan P{};
   if (space == SP_H1) {
     plan_add(P, FLD_DETJ, 1, 0, 0, 0, 0, 0, 0);
@@ -129,6 +132,11 @@ constexpr Plan make_plan(int space, int a, int b) {
                  ca != 0, ca != 1, ca != 2, cb != 0, cb != 1, cb != 2);
       }
   }
+  return P;
+}
+
+// Fields, q slots and groups of the terms in P.
+constexpr void plan_finish(Plan& P) {
   for (int i = 0; i < P.nt; ++i) {
     int f = -1;
     for (int j = 0; j < P.nf; ++j)
@@ -153,6 +161,28 @@ constexpr Plan make_plan(int space, int a, int b) {
     if (g < 0) { g = P.ng++; P.gr1[g] = P.qr1[q]; P.gs1[g] = P.qs1[q]; }
     P.qg[q] = g;
   }
+}
+
+constexpr Plan make_plan(int space, int a, int b) {
+  Plan P = plan_terms(space, a, b);
+  plan_finish(P);
+  return P;
+}
+
+// Extruded maps (the second form of (2.89)): x1 depends on xi1 alone, through a
+// constant lambda1, and (x2, x3) on (xi2, xi3) alone, so J, D = J^-1 J^-T and
+// C = J^T J are block diagonal and their (1,2), (1,3) entries vanish.  The
+// block's terms without those fields, regrouped.
+constexpr bool ext_vanishes(int f) {
+  return (fld_is_D(f) || fld_is_C(f)) && (f - (fld_is_D(f) ? FLD_D11 : FLD_C11) == 3 ||
+                                          f - (fld_is_D(f) ? FLD_D11 : FLD_C11) == 4);
+}
+constexpr Plan make_ext_plan(int space, int a, int b) {
+  const Plan T = plan_terms(space, a, b);
+  Plan P{};
+  for (int i = 0; i < T.nt; ++i)
+    if (!ext_vanishes(T.t[i].field)) P.t[P.nt++] = T.t[i];
+  plan_finish(P);
   return P;
 }
 

@@ -33,7 +33,7 @@ static int nslab(int space, int p) {
   return o;
 }
 
-Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, int64_t n) {
+Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int64_t n) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   dpg::Sched best;
   if (ctx->tune.empty()) return best;
@@ -41,7 +41,7 @@ Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, bool reduced, 
   int bestd = 3;
   for (const auto& kv : ctx->tune) {
     const TuneKey& k = kv.first;
-    if (k.space != space || k.p != p || k.prec != prec || k.reduced != int(reduced)) continue;
+    if (k.space != space || k.p != p || k.prec != prec || k.reduced != path) continue;
     const int d = std::abs(k.size_class - sc);
     if (d < bestd) { bestd = d; best = Sched{kv.second.slab_group, kv.second.diag}; }
   }
@@ -80,7 +80,7 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
-  const bool red = dpg::use_reduced(geom, o);
+  const int red = dpg::path_code(geom, o);
   std::vector<int> diags = {-1};
   if (!red) diags = dpg::diag_inline_ok(space, p) ? std::vector<int>{0, 1} : std::vector<int>{0};
   dpg::Sched best;
@@ -108,7 +108,7 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->tune[dpg::TuneKey{space, p, o.prec, int(red), dpg::size_class(n)}] = dpg::TuneVal{best.slab_group, best_ms, best.diag};
+    ctx->tune[dpg::TuneKey{space, p, o.prec, red, dpg::size_class(n)}] = dpg::TuneVal{best.slab_group, best_ms, best.diag};
   }
   if (slab_group) *slab_group = best.slab_group;
   return DPG_OK;
@@ -175,7 +175,7 @@ int dpg_tune_load(dpg_ctx* ctx, const char* path) {
 
 int dpg_tune_lookup(const dpg_ctx* ctx, int space, int p, int prec, int reduced, int64_t n_elem) {
   if (!ctx || !dpg::valid_space(space)) return -1;
-  return dpg::tuned_sched(ctx, space, p, prec, reduced != 0, n_elem).slab_group;
+  return dpg::tuned_sched(ctx, space, p, prec, reduced, n_elem).slab_group;
 }
 
 }  // extern "C"

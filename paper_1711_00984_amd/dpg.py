@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libdpg.so")
 H1, HCURL, HDIV, L2 = 0, 1, 2, 3
 SPACES = {"H1": H1, "HCURL": HCURL, "HDIV": HDIV, "L2": L2}
 FP64, FP32 = 0, 1
-TRILINEAR, AFFINE = 0, 1
+TRILINEAR, AFFINE, EXTRUDED = 0, 1, 2
+KINDS = {"trilinear": TRILINEAR, "affine": AFFINE, "extruded": EXTRUDED}
+GEOM_STRIDE = {TRILINEAR: 24, AFFINE: 12, EXTRUDED: 10}
 PATH_AUTO, PATH_GENERAL, PATH_REDUCED = 0, 1, 2
 PATHS = {"auto": PATH_AUTO, "general": PATH_GENERAL, "reduced": PATH_REDUCED}
 P_MAX = 11
@@ -187,8 +189,10 @@ def _stream_ptr(stream):
 def _geometry(geom, kind):
     if not (geom.is_cuda and geom.dtype == torch.float64 and geom.is_contiguous()):
         raise ValueError("geometry must be a contiguous float64 CUDA tensor")
-    kind = {"trilinear": TRILINEAR, "affine": AFFINE}.get(kind, kind)
-    per = 24 if kind == TRILINEAR else 12
+    kind = KINDS.get(kind, kind)
+    if kind not in GEOM_STRIDE:
+        raise ValueError(f"unknown geometry kind {kind}")
+    per = GEOM_STRIDE[kind]
     if geom.numel() % per:
         raise ValueError(f"geometry size {geom.numel()} is not a multiple of {per}")
     return Geometry(kind, 0, geom.numel() // per, geom.data_ptr())
@@ -333,8 +337,8 @@ class Server:
         tensor (host or device) of n_elem * 24 (trilinear) or * 12 (affine)
         values, copied before this returns.  Raises DpgError (code EAGAIN when
         the queue or the element slots are full)."""
-        kind = {"trilinear": TRILINEAR, "affine": AFFINE}.get(kind, kind)
-        per = 24 if kind == TRILINEAR else 12
+        kind = KINDS.get(kind, kind)
+        per = GEOM_STRIDE.get(kind, 24)
         if isinstance(geom, torch.Tensor):
             if geom.dtype != torch.float64 or not geom.is_contiguous():
                 raise ValueError("geometry must be a contiguous float64 tensor")
