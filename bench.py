@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_general_h1_p7_4096.json")
-KERNEL_SOURCES = ["gram_general.inc.h", "terms.h", "kernels.h", "gram_general_h1.hip"]
+KERNEL_SOURCES = ["gram_general.inc.h", "metric.h", "terms.h", "kernels.h", "gram_general_h1.hip"]
 
 
 def log(*a):
@@ -217,7 +217,7 @@ def main():
 
 
 def run_extra(ctx, dpg, stream, E, X, out64):
-    """FP32 on the benchmark workload; affine reduced vs general (H(curl), H(div));
+    """FP32 on the benchmark workload; affine and extruded reduced vs general;
     an uneven-order batch.  Small repeat counts; every rate is elements/s."""
     import numpy as np
     import torch
@@ -258,6 +258,28 @@ def run_extra(ctx, dpg, stream, E, X, out64):
             del o, A
             torch.cuda.empty_cache()
     res["affine_reduced_vs_general"] = aff
+
+    # extruded elements (quadrilaterals extruded along x1): reduced (exact xi1 integrals) vs general
+    ext = []
+    for space, p in (("H1", 4), ("H1", 7), ("HCURL", 6), ("HDIV", 6), ("L2", 8)):
+        mm = dpg.packed_len(space, p)
+        n_e = int(min(4096, (4 << 30) // (mm * 8)))
+        X_e = torch.from_numpy(meshgen.extruded_prisms(n_e, seed=1716)).cuda()
+        o = torch.empty(n_e * mm, dtype=torch.float64, device="cuda")
+        row = {"space": space, "p": p, "n_elem": n_e}
+        for path in ("reduced", "general"):
+            ctx.autotune(space, p, X_e, kind="extruded", out=o, path=path, stream=stream)
+            w, pr = time_launches(lambda: ctx.gram(space, p, X_e, kind="extruded", out=o, path=path,
+                                                   stream=stream), 5, 1, stream)
+            kk = float(np.mean(pr))
+            row[path] = {"elements_per_s": round(n_e * 5 / w, 1), "kernel_ms": round(kk, 4),
+                         "hbm_gbs": round((mm * 8 + 80) * n_e / (kk * 1e-3) / 1e9, 1),
+                         "hbm_frac": round((mm * 8 + 80) * n_e / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        ext.append(row)
+        log(f"[bench] extra extruded {row}")
+        del o, X_e
+        torch.cuda.empty_cache()
+    res["extruded_reduced_vs_general"] = ext
 
     # uneven batch, scaled-down version of the 50,000-element mixed run
     n_b = 8000
