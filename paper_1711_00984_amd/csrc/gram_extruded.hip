@@ -18,11 +18,12 @@
 // with xi2 or xi3 vanish on these maps and are dropped (make_ext_plan).
 //
 // Work decomposition: the column slabs of the general path.  Per slab and block
-// (a, b), the workgroup evaluates the fields at the L^2 points (FP64), contracts
-// xi3 then xi2 into K (FP64, stored once in the output precision) in LDS, and the
-// four waves stream the rows of component a of the slab's packed columns, 64
-// consecutive entries per store.  Only F K products remain per output entry, so
-// the kernel is bound by the HBM writes, like the constant-Jacobian path.
+// (a, b), a <= b, the workgroup evaluates the fields at the L^2 points (FP64) and
+// contracts xi3 then xi2 into K (FP64, stored once in the output precision) in
+// LDS; with the K of every block resident, the four waves stream the slab's
+// packed columns whole, across the components, 64 consecutive entries per store.
+// Only F K products remain per output entry, so the kernel is bound by the HBM
+// writes, like the constant-Jacobian path.
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -59,9 +60,20 @@ template <int S, int P> struct XShape {
   static constexpr int NT = over([](int a, int b) { return make_ext_plan(S, a, b).nt; });
   static constexpr int NG = over([](int a, int b) { return make_ext_plan(S, a, b).ng; });
   static constexpr int R3 = over([](int a, int) { return range1d(S, P, a, 2); });
-  static constexpr int K_LEN = over([](int a, int b) {
+  // K of block (a, b) and its offset among the blocks a' <= b of component b
+  static constexpr int KSZ(int a, int b) {
     return make_ext_plan(S, a, b).ng * range1d(S, P, a, 2) * range1d(S, P, b, 1) * range1d(S, P, a, 1);
-  });
+  }
+  static constexpr int KOFF(int a, int b) {
+    int o = 0;
+    for (int c = 0; c < a; ++c) o += KSZ(c, b);
+    return o;
+  }
+  static constexpr int K_LEN = [] {
+    int m = 0;
+    for (int b = 0; b < NC; ++b) m = KOFF(b + 1, b) > m ? KOFF(b + 1, b) : m;
+    return m;
+  }();
 };
 
 template <int S, int A, int B> struct XPlan {
@@ -90,7 +102,7 @@ struct XSmem {
 template <int S, int P, typename Real, int A, int B>
 __device__ __forceinline__ void build_k(const GeneralArgs& ga, const XSmem& sm, int j3, Real* sK) {
   using Sh = XShape<S, P>;
-  constexpr Plan PL = XPlan<S, A, B>::PL;
+  using XP = XPlan<S, A, B>;   // static members: lambdas capture nothing of the plan
   constexpr int L = Sh::L, L2 = L * L, KTL = KT * L;
   constexpr int R2a = Sh::R(A, 1), R2b = Sh::R(B, 1), R3a = Sh::R(A, 2);
   const int tid = threadIdx.x;
@@ -103,39 +115,39 @@ __device__ __forceinline__ void build_k(const GeneralArgs& ga, const XSmem& sm, 
     if (!(det > 0.0)) *sm.bad = 1;
     const double idet = 1.0 / det;
     const double wq = sm.w[m] * sm.w[n];
-    sfor<PL.nf>([&](auto F) {
+    sfor<XP::PL.nf>([&](auto F) {
       constexpr int f = decltype(F)::value;
-      constexpr int fid = PL.fid[f];
+      constexpr int fid = XP::PL.fid[f];
       sm.fld[f * L2 + pt] = field_value(fid, J, adj, det, idet) * wq * (field_weight(S, fid) ? ga.w1 : ga.w0);
     });
   }
   __syncthreads();
   // xi3: A_t[i3][m] = sum_n c_t(m, n) T^<r3>_{i3+sa3}(z_n) T^<s3>_{j3+sb3}(z_n)
-  for (int it = tid; it < PL.nt * R3a * L; it += NT_EXT) {
+  for (int it = tid; it < XP::PL.nt * R3a * L; it += NT_EXT) {
     const int m = it % L, i3 = (it / L) % R3a, t = it / (L * R3a);
     double acc = 0.0;
-    sfor<PL.nt>([&](auto TT) {
+    sfor<XP::PL.nt>([&](auto TT) {
       constexpr int tt = decltype(TT)::value;
       if (t != tt) return;
-      const double* ti = sm.T + PL.t[tt].r[2] * KTL + (i3 + Sh::SH(A, 2)) * L;
-      const double* tj = sm.T + PL.t[tt].s[2] * KTL + (j3 + Sh::SH(B, 2)) * L;
-      const double* c = sm.fld + PL.tf[tt] * L2 + m * L;
+      const double* ti = sm.T + XP::PL.t[tt].r[2] * KTL + (i3 + Sh::SH(A, 2)) * L;
+      const double* tj = sm.T + XP::PL.t[tt].s[2] * KTL + (j3 + Sh::SH(B, 2)) * L;
+      const double* c = sm.fld + XP::PL.tf[tt] * L2 + m * L;
 #pragma unroll
       for (int n = 0; n < L; ++n) acc += c[n] * ti[n] * tj[n];
-      acc *= double(PL.t[tt].sign);
+      acc *= double(XP::PL.t[tt].sign);
     });
     sm.A[(t * Sh::R3 + i3) * L + m] = acc;
   }
   __syncthreads();
   // xi2: K_g[i3][j2][i2] = sum_{t in g} sum_m A_t[i3][m] T^<r2>_{i2+sa2}(z_m) T^<s2>_{j2+sb2}(z_m)
-  for (int it = tid; it < PL.ng * R3a * R2b * R2a; it += NT_EXT) {
+  for (int it = tid; it < XP::PL.ng * R3a * R2b * R2a; it += NT_EXT) {
     const int i2 = it % R2a, j2 = (it / R2a) % R2b, i3 = (it / (R2a * R2b)) % R3a, g = it / (R2a * R2b * R3a);
     double acc = 0.0;
-    sfor<PL.nt>([&](auto TT) {
+    sfor<XP::PL.nt>([&](auto TT) {
       constexpr int tt = decltype(TT)::value;
-      if (PL.qg[PL.tq[tt]] != g) return;
-      const double* ti = sm.T + PL.t[tt].r[1] * KTL + (i2 + Sh::SH(A, 1)) * L;
-      const double* tj = sm.T + PL.t[tt].s[1] * KTL + (j2 + Sh::SH(B, 1)) * L;
+      if (XP::PL.qg[XP::PL.tq[tt]] != g) return;
+      const double* ti = sm.T + XP::PL.t[tt].r[1] * KTL + (i2 + Sh::SH(A, 1)) * L;
+      const double* tj = sm.T + XP::PL.t[tt].s[1] * KTL + (j2 + Sh::SH(B, 1)) * L;
       const double* a = sm.A + (tt * Sh::R3 + i3) * L;
 #pragma unroll
       for (int m = 0; m < L; ++m) acc += a[m] * ti[m] * tj[m];
@@ -145,30 +157,37 @@ __device__ __forceinline__ void build_k(const GeneralArgs& ga, const XSmem& sm, 
   __syncthreads();
 }
 
-// Rows of component A of the packed columns of slab (B, j3): wave w takes the
-// columns c = w, w + 4, ...; its lanes walk the rows contiguously.
-template <int S, int P, typename Real, int A, int B>
-__device__ __forceinline__ void stream_rows(const Real* sF, const Real* sK, int j3, Real* __restrict__ outp) {
+// Packed columns of slab (B, j3), whole: wave w takes the columns c = w, w + 4, ...;
+// its lanes walk the rows 0..J contiguously, across the components A <= B, whose
+// K blocks are all resident.
+template <int S, int P, typename Real, int B>
+__device__ __forceinline__ void stream_cols(const Real* sF, const Real* sK, int j3, Real* __restrict__ outp) {
   using Sh = XShape<S, P>;
-  constexpr Plan PL = XPlan<S, A, B>::PL;
-  constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1), R3a = Sh::R(A, 2);
   constexpr int R1b = Sh::R(B, 0), R2b = Sh::R(B, 1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int c = wave; c < R1b * R2b; c += 4) {
     const int j1 = c % R1b, j2 = c / R1b;
     const int J = Sh::OFF(B) + R1b * R2b * j3 + c;
-    const int I1 = A < B ? Sh::OFF(A) + R1a * R2a * R3a : J + 1;   // rows [OFF(A), I1)
     Real* col = outp + int64_t(J) * (J + 1) / 2;
     const int b1 = j1 + Sh::SH(B, 0);
-    for (int I = Sh::OFF(A) + lane; I < I1; I += 64) {
-      const int loc = I - Sh::OFF(A);
-      const int i1 = loc % R1a, i2 = (loc / R1a) % R2a, i3 = loc / (R1a * R2a);
-      const int a1 = i1 + Sh::SH(A, 0);
+    for (int I = lane; I <= J; I += 64) {
       Real v = Real(0);
-      sfor<PL.ng>([&](auto GG) {
-        constexpr int g = decltype(GG)::value;
-        const Real f = sF[((2 * PL.gr1[g] + PL.gs1[g]) * KT + a1) * KT + b1];
-        v += f * sK[((g * R3a + i3) * R2b + j2) * R2a + i2];
+      sfor<B + 1>([&](auto AA) {
+        constexpr int A = decltype(AA)::value;
+        using XP = XPlan<S, A, B>;   // static members: nothing of the plan is captured
+        constexpr int R1a = Sh::R(A, 0), R2a = Sh::R(A, 1), R3a = Sh::R(A, 2);
+        if (I < Sh::OFF(A) || I >= Sh::OFF(A + 1)) return;
+        const int loc = I - Sh::OFF(A);
+        const int i1 = loc % R1a, i2 = (loc / R1a) % R2a, i3 = loc / (R1a * R2a);
+        const int a1 = i1 + Sh::SH(A, 0);
+        constexpr int ko = Sh::KOFF(A, B);   // constexpr: evaluated by the compiler, not per row
+        const Real* k = sK + ko;
+        sfor<XP::PL.ng>([&](auto GG) {
+          constexpr int g = decltype(GG)::value;
+          constexpr int tab = 2 * XP::PL.gr1[g] + XP::PL.gs1[g];
+          const Real f = sF[(tab * KT + a1) * KT + b1];
+          v += f * k[((g * R3a + i3) * R2b + j2) * R2a + i2];
+        });
       });
       col[I] = v;
     }
@@ -214,12 +233,12 @@ __global__ void __launch_bounds__(NT_EXT) k_extruded(GeneralArgs ga) {
       const int j3 = s - Sh::slab0(b);
       sfor<b + 1>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
-        if (bad) return;
-        build_k<S, P, Real, a, b>(ga, sm, j3, s_K);
-        bad = s_bad != 0;   // uniform: read after the barrier that closes build_k
-        if (!bad) stream_rows<S, P, Real, a, b>(s_F, s_K, j3, outp);
-        __syncthreads();    // s_K and the field buffers are rebuilt for the next block
+        constexpr int ko = Sh::KOFF(a, b);
+        build_k<S, P, Real, a, b>(ga, sm, j3, s_K + ko);
       });
+      bad = s_bad != 0;   // uniform: read after the barrier that closes the last build_k
+      if (!bad) stream_cols<S, P, Real, b>(s_F, s_K, j3, outp);
+      __syncthreads();    // s_K and the field buffers are rebuilt for the next slab
     });
   }
   if (bad) {
