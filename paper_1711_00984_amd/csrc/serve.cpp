@@ -30,7 +30,7 @@ static_assert(kMaxMerge == SERVE_MAX_MERGE, "merge limit of the scheduler and of
 namespace {
 
 int elem_size(int prec) { return prec == DPG_FP32 ? 4 : 8; }
-int geom_stride(int kind) { return kind == DPG_GEOM_AFFINE ? 12 : 24; }
+int geom_stride(int kind) { return kind == DPG_GEOM_AFFINE ? 12 : kind == DPG_GEOM_EXTRUDED ? 10 : 24; }
 
 class HipExecutor final : public Executor {
  public:
@@ -42,14 +42,15 @@ class HipExecutor final : public Executor {
     e = hipMalloc(reinterpret_cast<void**>(&out_), size_t(cfg.mem_budget_bytes));
     if (e != hipSuccess)
       return fail(DPG_ENOMEM, "output arena of %lld bytes: %s", (long long)cfg.mem_budget_bytes, hipGetErrorString(e));
-    const size_t per_slot = (24 + 12) * sizeof(double) + sizeof(int32_t) + sizeof(int64_t) + 2 * sizeof(int32_t);
+    const size_t per_slot = (24 + 12 + 10) * sizeof(double) + sizeof(int32_t) + sizeof(int64_t) + 2 * sizeof(int32_t);
     char* base = nullptr;
     e = hipMalloc(reinterpret_cast<void**>(&base), size_t(slots_) * per_slot);
     if (e != hipSuccess) return fail(DPG_ENOMEM, "slot arena: %s", hipGetErrorString(e));
     slot_mem_ = base;
     geo_tri_ = reinterpret_cast<double*>(base);
     geo_aff_ = geo_tri_ + 24 * slots_;
-    off_ = reinterpret_cast<int64_t*>(geo_aff_ + 12 * slots_);
+    geo_ext_ = geo_aff_ + 12 * slots_;
+    off_ = reinterpret_cast<int64_t*>(geo_ext_ + 10 * slots_);
     status_ = reinterpret_cast<int32_t*>(off_ + slots_);
     ids_ = status_ + slots_;
     for (int i = 0; i < n_streams_; ++i) {
@@ -85,7 +86,7 @@ class HipExecutor final : public Executor {
       *staged = true;
       return DPG_OK;
     }
-    double* dst = (rq.geom.kind == DPG_GEOM_AFFINE ? geo_aff_ : geo_tri_) + slot0 * st;
+    double* dst = arena(rq.geom.kind) + slot0 * st;
     std::lock_guard<std::mutex> lk(upload_mu_);
     hipError_t e = hipSetDevice(ctx_->device);
     if (e == hipSuccess)
@@ -106,7 +107,7 @@ class HipExecutor final : public Executor {
     o.path = w0.path;
     o.w0 = w0.w0;
     o.w1 = w0.w1;
-    double* geo = w0.kind == DPG_GEOM_AFFINE ? geo_aff_ : geo_tri_;
+    double* geo = arena(w0.kind);
     const int gs = geom_stride(w0.kind);
     for (const Work& w : l.work) {   // staged host geometry goes up first, in stream order
       if (!w.staged) continue;
@@ -212,8 +213,12 @@ class HipExecutor final : public Executor {
   int n_streams_;
   char* out_ = nullptr;
   char* slot_mem_ = nullptr;
-  double* geo_tri_ = nullptr;
+  double* geo_tri_ = nullptr;   // [slots][24] trilinear, [slots][12] affine, [slots][10] extruded
   double* geo_aff_ = nullptr;
+  double* geo_ext_ = nullptr;
+  double* arena(int kind) const {
+    return kind == DPG_GEOM_AFFINE ? geo_aff_ : kind == DPG_GEOM_EXTRUDED ? geo_ext_ : geo_tri_;
+  }
   int64_t* off_ = nullptr;
   int32_t* status_ = nullptr;
   int32_t* ids_ = nullptr;

@@ -115,10 +115,10 @@ int Server::submit(const dpg_request& rq, uint64_t* ticket) {
   if (rq.prec != DPG_FP64 && rq.prec != DPG_FP32) return reject(fail(DPG_EINVAL, "unknown precision %d", rq.prec));
   if (rq.path < DPG_PATH_AUTO || rq.path > DPG_PATH_REDUCED)
     return reject(fail(DPG_EINVAL, "unknown path %d", rq.path));
-  if (rq.geom.kind != DPG_GEOM_TRILINEAR && rq.geom.kind != DPG_GEOM_AFFINE)
+  if (rq.geom.kind != DPG_GEOM_TRILINEAR && rq.geom.kind != DPG_GEOM_AFFINE && rq.geom.kind != DPG_GEOM_EXTRUDED)
     return reject(fail(DPG_EINVAL, "unknown geometry kind %d", rq.geom.kind));
-  if (rq.path == DPG_PATH_REDUCED && rq.geom.kind != DPG_GEOM_AFFINE)
-    return reject(fail(DPG_EINVAL, "the reduced path needs affine geometry"));
+  if (rq.path == DPG_PATH_REDUCED && rq.geom.kind == DPG_GEOM_TRILINEAR)
+    return reject(fail(DPG_EINVAL, "the reduced path needs affine or extruded geometry"));
   if (rq.geom.n_elem < 1 || !rq.geom.data) return reject(fail(DPG_EINVAL, "empty request or NULL geometry"));
   if (!std::isfinite(rq.w0) || !std::isfinite(rq.w1)) return reject(fail(DPG_EINVAL, "weights must be finite"));
   const int pr = rq.p + rq.dp;

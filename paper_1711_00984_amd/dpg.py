@@ -334,8 +334,8 @@ class Server:
 
     def submit(self, space, p, geom, dp=0, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0):
         """Queue one request; returns its ticket.  geom: float64 numpy array or
-        tensor (host or device) of n_elem * 24 (trilinear) or * 12 (affine)
-        values, copied before this returns.  Raises DpgError (code EAGAIN when
+        tensor (host or device) of n_elem * 24 (trilinear), * 12 (affine) or
+        * 10 (extruded) values, copied before this returns.  Raises DpgError (code EAGAIN when
         the queue or the element slots are full)."""
         kind = KINDS.get(kind, kind)
         per = GEOM_STRIDE.get(kind, 24)

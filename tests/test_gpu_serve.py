@@ -147,6 +147,24 @@ def test_affine_reduced_and_device_geometry(ctx, dpg):
     srv.close()
 
 
+def test_extruded_requests_match_alone(ctx, dpg):
+    say("extruded requests")
+    srv = dpg.Server(ctx, mem_budget_bytes=1 << 30)
+    E1 = meshgen.extruded_prisms(120, seed=51)
+    E2 = meshgen.extruded_prisms(80, seed=52)
+    Ed = torch.from_numpy(E2.reshape(-1).copy()).cuda()
+    torch.cuda.synchronize()
+    t1 = srv.submit("HCURL", 4, E1.reshape(-1), kind="extruded")               # host geometry, reduced path
+    t2 = srv.submit("H1", 5, Ed, kind="extruded", prec="fp32", path="general")  # device geometry, general path
+    drain(srv, [t1, t2])
+    torch.cuda.synchronize()
+    assert torch.equal(srv.read(t1), alone(ctx, "HCURL", 4, E1, kind="extruded"))
+    g = torch.from_numpy(E2).cuda()
+    assert torch.equal(srv.read(t2), ctx.gram("H1", 5, g, kind="extruded", prec="fp32", path="general"))
+    oracle_check(srv.read(t1).cpu().numpy(), 7, "HCURL", 4, meshgen.extruded_as_trilinear(E1))
+    srv.close()
+
+
 def test_bad_element_flagged_in_served_result(ctx, dpg):
     say("bad element served")
     srv = dpg.Server(ctx, mem_budget_bytes=1 << 28)

@@ -17,7 +17,7 @@ dpg = load_binding()
 
 
 def geom(n, kind="trilinear"):
-    return np.zeros(n * (24 if kind == "trilinear" else 12))
+    return np.zeros(n * {"trilinear": 24, "affine": 12, "extruded": 10}[kind])
 
 
 def req_bytes(space, pr, n, prec="fp64"):
@@ -190,7 +190,8 @@ def test_invalid_requests_rejected_at_submit():
         dict(space="H1", p=3, dp=-1, geom=geom(1)),
         dict(space="H1", p=3, geom=geom(1), prec=5),
         dict(space="H1", p=3, geom=geom(1), path=9),
-        dict(space="H1", p=3, geom=geom(1), path="reduced"),   # reduced needs affine geometry
+        dict(space="H1", p=3, geom=geom(1), path="reduced"),   # reduced needs affine or extruded geometry
+        dict(space="H1", p=3, geom=geom(1), kind=3),            # unknown geometry kind
         dict(space="H1", p=3, geom=geom(1), w0=float("nan")),
         dict(space="HCURL", p=8, geom=geom(4)),                # output > 1 MiB budget: split it
         dict(space="L2", p=2, geom=geom(1001)),                # more elements than slots
@@ -203,6 +204,16 @@ def test_invalid_requests_rejected_at_submit():
     with pytest.raises(ValueError):
         s.submit("H1", 3, np.zeros(25))
     assert s.stats()["rejected"] == len(bad) and s.stats()["submitted"] == 0
+    s.close()
+
+
+def test_extruded_requests_accepted():
+    """Extruded geometry (10 doubles per element) is served by either path."""
+    s = dpg.Server(None, mem_budget_bytes=1 << 26, max_slots=1000, test_executor=True)
+    t = [s.submit("HDIV", 3, geom(5, "extruded"), kind="extruded"),
+         s.submit("HDIV", 3, geom(5, "extruded"), kind="extruded", path="general")]
+    res = drain(s, t)
+    assert all(r["status"] == dpg.OK and r["n_elem"] == 5 for r in res.values())
     s.close()
 
 
