@@ -332,13 +332,14 @@ def _force_schedule(ctx, tmp_path, space, p, prec, n, G, diag):
     ctx.tune_load(f)
 
 
-@pytest.mark.parametrize("space,p", [("H1", 7), ("L2", 8), ("HCURL", 4), ("H1", 9)])
+@pytest.mark.parametrize("space,p", [("H1", 7), ("L2", 8), ("HCURL", 4), ("H1", 9), ("HDIV", 6), ("HCURL", 5)])
 def test_every_schedule_agrees(ctx, dpg, tmp_path, space, p):
     """Slab groups move the workgroup boundaries; the diagonal schedule moves the
     diagonal pairs between their own triangular-tile batches and the end of each
     slab (full tile, lower triangle dropped).  Every combination must give the same
     output bit for bit, and the oracle within the FP64 / FP32 tolerances (p <= 7).
-    Covers two pairs per row tile (H1 7), one (L2 8, H1 9) and several blocks."""
+    Covers two pairs per row tile (H1 7), one (L2 8, H1 9) and three-component spaces
+    (H(curl) 4, 5, H(div) 6)."""
     say(f"schedules {space} p={p}")
     n = 5
     X = meshgen.perturbed_hexes(n, seed=81)
