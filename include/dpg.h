@@ -158,6 +158,33 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
                                const dpg_geometry* geom, const int64_t* out_offset, void* out,
                                const dpg_opts* opts, void* stream);
 
+/* Coupling block of the adjoint graph inner product of the ultraweak
+ * formulation (Section 3.3, (3.17), (3.18)), whose test space is H1 x H(div):
+ *   C[I][J] = int_K (v_J . grad q_I - q_I div v_J) dx,  q_I in W^p, v_J in V^p.
+ * The Piola maps cancel every Jacobian, so C is the same for every element and
+ * is computed exactly from the 1D integrals F^{rs}:
+ *   C[I][J] = prod_{d != b} F^01_{i_d, j_d+1} (F^10_{i_b, j_b} - F^01_{i_b, j_b})
+ * for component b of v_J.  out: device, dense row-major [dim W^p][dim V^p]
+ * (dpg_gram_dim), FP64 or FP32 by prec.  With the H1 and H(div) Grams for
+ * w0 = omega^2 + alpha, w1 = 1, the adjoint graph Gram of (3.17) is
+ *   [[G_H1, -i omega C], [i omega C^T, G_Hdiv]]
+ * (rows: first argument (dq, dv), columns: second argument (q, v)).
+ * Asynchronous on stream.  Errors: DPG_EINVAL (p outside [1, p_max], null out,
+ * prec), DPG_ENOTINIT, DPG_EHIP. */
+int dpg_adjoint_coupling(const dpg_ctx* ctx, int p, void* out, int prec, void* stream);
+
+/* Vector-valued test spaces (Section 2.7, (2.85)-(2.88)): the Gram of the
+ * `copies`-fold product of a space (the vector H1, H(div), ... of the
+ * applications) is block diagonal, with the scalar Gram on each diagonal block.
+ * Expands n_elem packed Grams of dimension n (src: consecutive 'U' packed,
+ * n (n+1)/2 entries each) into packed Grams of dimension copies * n (dst,
+ * consecutive, basis ordered copy by copy), zero off the diagonal blocks.
+ * 1 <= copies <= 4; src and dst are device memory of the precision prec and
+ * must not overlap.  Asynchronous on stream.  Errors: DPG_EINVAL (sizes,
+ * copies, overlap, null pointers, prec), DPG_ENOTINIT, DPG_EHIP. */
+int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copies, const void* src, void* dst,
+                         int prec, void* stream);
+
 /* Autotuning of the work decomposition (column slabs per workgroup, the
  * kernels' tile shape along the packed output; on the general path also the
  * schedule of the diagonal (i3 = j3) pairs: after all others with a

@@ -92,6 +92,34 @@ def gram(space, p, kind, geom, L=None, w0=1.0, w1=1.0):
     return G
 
 
+def vector_gram(space, p, kind, geom, copies, L=None, w0=1.0, w1=1.0):
+    """Gram of the `copies`-fold product of a space (Section 2.7): basis
+    functions e_k (x) f_I, k < copies, ordered copy by copy, with the Frobenius
+    inner products of (2.85) and (2.87), (div Theta_I)^T (div Theta_J) for the
+    derivative part.  Built from the matrix-valued fields directly, without the
+    block structure that (2.86) and (2.88) derive."""
+    xi, wq = _rule(space, p, L)
+    f, g, detJ = physical_fields(space, p, kind, geom, xi)
+    W = wq * detJ
+    Q, n = f.shape[0], f.shape[1]
+
+    def lift(h):
+        out = np.zeros((Q, copies * n, copies * h.shape[2]))
+        for k in range(copies):
+            out[:, k * n:(k + 1) * n, k * h.shape[2]:(k + 1) * h.shape[2]] = h
+        return out
+
+    F = lift(f)
+    G = np.zeros((copies * n, copies * n))
+    for c in range(F.shape[2]):
+        G += w0 * ((F[:, :, c] * W[:, None]).T @ F[:, :, c])
+    if g is not None and w1 != 0.0:
+        Gd = lift(g)
+        for c in range(Gd.shape[2]):
+            G += w1 * ((Gd[:, :, c] * W[:, None]).T @ Gd[:, :, c])
+    return G
+
+
 def gram_entries(space, p, kind, geom, I, J, L=None, w0=1.0, w1=1.0):
     """G_IJ for the index lists I, J (same length), computed entry by entry."""
     I = np.asarray(I, dtype=np.int64)

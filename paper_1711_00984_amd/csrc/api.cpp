@@ -209,4 +209,30 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
                               static_cast<hipStream_t>(stream));
 }
 
+int dpg_adjoint_coupling(const dpg_ctx* ctx, int p, void* out, int prec, void* stream) {
+  if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
+  if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
+  if (!out) return fail(DPG_EINVAL, "output is NULL");
+  if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
+  const void* F = prec == DPG_FP32 ? static_cast<const void*>(ctx->d_f32) : static_cast<const void*>(ctx->d_f64);
+  const hipError_t e = dpg::launch_coupling(p, prec, F, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPG_OK : hip_fail(e, "coupling launch");
+}
+
+int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copies, const void* src, void* dst,
+                         int prec, void* stream) {
+  if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
+  if (n_elem < 0 || n < 1) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
+  if (copies < 1 || copies > 4) return fail(DPG_EINVAL, "copies=%d outside [1, 4]", copies);
+  if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
+  if (n_elem == 0) return DPG_OK;
+  if (!src || !dst) return fail(DPG_EINVAL, "source or destination is NULL");
+  const int64_t es = prec == DPG_FP32 ? 4 : 8, cn = n * copies;
+  const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+  const uintptr_t s1 = s0 + uintptr_t(n_elem * (n * (n + 1) / 2) * es), d1 = d0 + uintptr_t(n_elem * (cn * (cn + 1) / 2) * es);
+  if (s0 < d1 && d0 < s1) return fail(DPG_EINVAL, "source and destination overlap");
+  const hipError_t e = dpg::launch_replicate(prec, src, dst, n, copies, n_elem, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPG_OK : hip_fail(e, "replicate launch");
+}
+
 }  // extern "C"

@@ -61,6 +61,12 @@ hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t 
 // Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
 hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);
 
+// Adjoint graph coupling block C[dim W^p][dim V^p] (row-major) from the F tables of
+// the precision; block-diagonal replication of packed Grams (n -> copies * n).
+hipError_t launch_coupling(int p, int prec, const void* F, void* out, hipStream_t s);
+hipError_t launch_replicate(int prec, const void* src, void* dst, int64_t n, int copies, int64_t n_elem,
+                            hipStream_t s);
+
 // Reduced path for extruded elements (exact xi1 integrals, quadrature in xi2, xi3);
 // extruded geometry only.
 hipError_t launch_extruded(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);

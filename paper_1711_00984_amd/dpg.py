@@ -94,6 +94,10 @@ _lib.dpg_gram_integrate_batched.restype = _i
 _lib.dpg_autotune.argtypes = [_vp, _i, _i, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp,
                               ctypes.POINTER(ctypes.c_int)]
 _lib.dpg_autotune.restype = _i
+_lib.dpg_adjoint_coupling.argtypes = [_vp, _i, _vp, _i, _vp]
+_lib.dpg_adjoint_coupling.restype = _i
+_lib.dpg_replicate_blocks.argtypes = [_vp, _i64, _i64, _i, _vp, _vp, _i, _vp]
+_lib.dpg_replicate_blocks.restype = _i
 _lib.dpg_tune_save.argtypes = [_vp, ctypes.c_char_p]
 _lib.dpg_tune_save.restype = _i
 _lib.dpg_tune_load.argtypes = [_vp, ctypes.c_char_p]
@@ -284,6 +288,33 @@ class Context:
 
     def batch_plans(self):
         return int(_lib.dpg_batch_plans(self._h))
+
+    def adjoint_coupling(self, p, prec="fp64", out=None, stream=None):
+        """Coupling block C[dim W^p, dim V^p] of the adjoint graph inner product
+        (dpg_adjoint_coupling), dense row-major on the device."""
+        pr = {"fp64": FP64, "fp32": FP32}.get(prec, prec)
+        shape = (gram_dim("H1", p), gram_dim("HDIV", p))
+        if min(shape) < 1:
+            raise DpgError(EINVAL, f"invalid order p={p}")
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64 if pr == FP64 else torch.float32, device="cuda")
+        _check(_lib.dpg_adjoint_coupling(self._h, p, out.data_ptr(), pr, _stream_ptr(stream)))
+        return out
+
+    def replicate_blocks(self, src, n, copies, prec="fp64", out=None, stream=None):
+        """Block-diagonal expansion of packed Grams of dimension n into dimension
+        copies * n (dpg_replicate_blocks); src holds n_elem packed Grams."""
+        pr = {"fp64": FP64, "fp32": FP32}.get(prec, prec)
+        m = n * (n + 1) // 2
+        if src.numel() % m:
+            raise ValueError(f"source size {src.numel()} is not a multiple of {m}")
+        ne = src.numel() // m
+        cn = n * copies
+        if out is None:
+            out = torch.empty(ne * (cn * (cn + 1) // 2), dtype=src.dtype, device="cuda")
+        _check(_lib.dpg_replicate_blocks(self._h, ne, n, copies, src.data_ptr(), out.data_ptr(), pr,
+                                         _stream_ptr(stream)))
+        return out
 
     def gram_batched(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
                      w0=1.0, w1=1.0, status=None, stream=None):

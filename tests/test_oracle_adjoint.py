@@ -60,3 +60,14 @@ def test_integration_by_parts_on_bubbles(p):
     # and the constant has no gradient: the vertex functions' A rows sum to zero
     vert = np.all(iq[:, 1:] <= 1, axis=1)
     assert np.abs(A[vert].sum(axis=0)).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("space,p,copies", [("H1", 2, 3), ("HDIV", 2, 3), ("HCURL", 1, 2), ("L2", 3, 3)])
+def test_vector_gram_is_block_diagonal(space, p, copies):
+    """(2.86), (2.88): the Gram of the product space is the scalar Gram on each
+    diagonal block and zero elsewhere."""
+    X = meshgen.perturbed_hexes(1, seed=230)[0]
+    from oracle import gram as og
+    V = og.vector_gram(space, p, "trilinear", X, copies)
+    G = og.gram(space, p, "trilinear", X)
+    assert np.abs(V - np.kron(np.eye(copies), G)).max() <= 1e-13 * np.abs(G).max()
