@@ -281,6 +281,26 @@ def run_extra(ctx, dpg, stream, E, X, out64):
         torch.cuda.empty_cache()
     res["extruded_reduced_vs_general"] = ext
 
+    # vector-valued test spaces: block-diagonal replication of packed Grams (copies = 3), HBM-bound copy
+    n_r, sp_r, p_r = 1024, "H1", 7
+    nn = dpg.gram_dim(sp_r, p_r)
+    src = torch.ones(n_r * (nn * (nn + 1) // 2), dtype=torch.float64, device="cuda")
+    dst = torch.empty(n_r * (3 * nn * (3 * nn + 1) // 2), dtype=torch.float64, device="cuda")
+    w, pr = time_launches(lambda: ctx.replicate_blocks(src, nn, 3, out=dst, stream=stream), 5, 1, stream)
+    kk = float(np.mean(pr))
+    moved = (src.numel() + dst.numel()) * 8
+    res["replicate_h1_p7_x3"] = {"n_elem": n_r, "kernel_ms": round(kk, 4), "gb_moved": round(moved / 1e9, 2),
+                                 "hbm_gbs": round(moved / (kk * 1e-3) / 1e9, 1),
+                                 "hbm_frac": round(moved / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    log(f"[bench] extra replicate {res['replicate_h1_p7_x3']}")
+    del src, dst
+    # adjoint graph coupling block (one constant matrix per order)
+    cpl = ctx.adjoint_coupling(11)
+    w, pr = time_launches(lambda: ctx.adjoint_coupling(11, out=cpl, stream=stream), 5, 1, stream)
+    res["adjoint_coupling_p11"] = {"shape": list(cpl.shape), "kernel_ms": round(float(np.mean(pr)), 4)}
+    del cpl
+    torch.cuda.empty_cache()
+
     # uneven batch, scaled-down version of the 50,000-element mixed run
     n_b = 8000
     sp, pr_, G = meshgen.mixed_batch(n_b, p_lo=2, p_hi=9, dp=1, seed=1714)
