@@ -185,6 +185,33 @@ int dpg_adjoint_coupling(const dpg_ctx* ctx, int p, void* out, int prec, void* s
 int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copies, const void* src, void* dst,
                          int prec, void* stream);
 
+/* Static condensation of the test variables (Section 1, (3.7)-(3.8)):
+ * eliminating s needs G^{-1} B, G^{-1} B~ and G^{-1} l, from a Cholesky
+ * factorization of each element's Gram and substitution with the factor.
+ *
+ * dpg_cholesky_packed factors n_elem Grams of dimension n in place: ap holds
+ * consecutive 'U' packed Grams (n (n+1)/2 entries each, as dpg_gram_integrate
+ * writes them) on entry and their factors U, G = U^T U with U upper
+ * triangular and a positive diagonal, in the same storage on exit (LAPACK
+ * dpptrf with uplo 'U').  info: optional device int32[n_elem], 0, or k > 0
+ * when the leading minor of order k of that element is not positive
+ * definite; then columns 0..k-2 of its U are final and the rest of its
+ * storage is unspecified.  Device memory of the precision prec; asynchronous
+ * on stream.  Errors: DPG_EINVAL (n outside [1, 65536], n_elem < 0, null ap,
+ * prec), DPG_ENOTINIT, DPG_EHIP. */
+int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap, int32_t* info, int prec,
+                        void* stream);
+
+/* Solves G X = B for each element with the factor from dpg_cholesky_packed:
+ * up holds the n_elem packed factors; b holds n_elem consecutive column-major
+ * n x nrhs blocks (leading dimension n, element e at b + e n nrhs) and is
+ * overwritten with X (LAPACK dpptrs).  up and b are device memory of the
+ * precision prec and must not overlap.  Asynchronous on stream.  Errors:
+ * DPG_EINVAL (n outside [1, 65536], nrhs outside [1, 2^26], n_elem < 0, null
+ * pointers, overlap, prec), DPG_ENOTINIT, DPG_EHIP. */
+int dpg_cholesky_solve_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, const void* up, int64_t nrhs, void* b,
+                              int prec, void* stream);
+
 /* Autotuning of the work decomposition (column slabs per workgroup, the
  * kernels' tile shape along the packed output; on the general path also the
  * schedule of the diagonal (i3 = j3) pairs: after all others with a

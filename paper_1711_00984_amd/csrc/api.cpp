@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "condense.h"
 #include "ctx.h"
 #include "tables.h"
 #include "terms.h"
@@ -233,6 +234,33 @@ int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copi
   if (s0 < d1 && d0 < s1) return fail(DPG_EINVAL, "source and destination overlap");
   const hipError_t e = dpg::launch_replicate(prec, src, dst, n, copies, n_elem, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DPG_OK : hip_fail(e, "replicate launch");
+}
+
+int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap, int32_t* info, int prec,
+                        void* stream) {
+  if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
+  if (n_elem < 0 || n < 1 || n > 65536) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
+  if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
+  if (n_elem == 0) return DPG_OK;
+  if (!ap) return fail(DPG_EINVAL, "packed Grams are NULL");
+  const hipError_t e = dpg::launch_potrf(prec, ap, n, n_elem, info, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPG_OK : hip_fail(e, "cholesky launch");
+}
+
+int dpg_cholesky_solve_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, const void* up, int64_t nrhs, void* b,
+                              int prec, void* stream) {
+  if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
+  if (n_elem < 0 || n < 1 || n > 65536) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
+  if (nrhs < 1 || nrhs > (int64_t(1) << 26)) return fail(DPG_EINVAL, "nrhs=%lld", (long long)nrhs);
+  if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
+  if (n_elem == 0) return DPG_OK;
+  if (!up || !b) return fail(DPG_EINVAL, "factor or right-hand side is NULL");
+  const int64_t es = prec == DPG_FP32 ? 4 : 8;
+  const uintptr_t u0 = reinterpret_cast<uintptr_t>(up), b0 = reinterpret_cast<uintptr_t>(b);
+  const uintptr_t u1 = u0 + uintptr_t(n_elem * (n * (n + 1) / 2) * es), b1 = b0 + uintptr_t(n_elem * n * nrhs * es);
+  if (u0 < b1 && b0 < u1) return fail(DPG_EINVAL, "factor and right-hand side overlap");
+  const hipError_t e = dpg::launch_potrs(prec, up, n, n_elem, nrhs, b, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPG_OK : hip_fail(e, "cholesky solve launch");
 }
 
 }  // extern "C"

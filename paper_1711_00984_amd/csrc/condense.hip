@@ -1,0 +1,326 @@
+// condense.hip -- the first consumer of the Grams on the device: static
+// condensation of the test variables s in (3.7) needs G^{-1} B, G^{-1} B~ and
+// G^{-1} l ((3.8), Section 1), which come from a Cholesky factorization of G
+// followed by forward and backward substitution.  The Grams stay where the
+// integration kernels wrote them ('U' packed, one per element), and the
+// factor overwrites them in place: G = U^T U, U upper triangular with a
+// positive diagonal (LAPACK's packed 'U' convention).
+//
+// One workgroup per element (per element and 16 right-hand sides for the
+// solve).  Both kernels walk 16-row blocks of a triangular solve with U^T:
+// each block first subtracts the product of the rows already finished (a
+// 16 x 16 x K contraction over packed columns, on FP64 or FP32 MFMA, the
+// 4-wide k steps dealt round robin to the four waves and summed through LDS),
+// then 16 lanes finish the block against its 16 x 16 diagonal block of U.
+// The factorization is the same walk with the Gram's own columns as
+// right-hand sides, one 16-column panel at a time (the up-looking order:
+// column j of U solves U[:j, :j]^T u = G[:j, j]), closed by the Cholesky
+// factor of the panel's diagonal block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "condense.h"
+
+namespace dpg {
+
+namespace {
+
+typedef double c4d __attribute__((ext_vector_type(4)));
+typedef float c4f __attribute__((ext_vector_type(4)));
+
+// v_mfma_*_16x16x4: lane i + 16 k holds A[i][k] and B[k][i]; accumulator
+// register r of lane (g = lane / 16, j = lane % 16) holds C[row(g, r)][j].
+template <typename Real> struct Mfma;
+template <> struct Mfma<double> {
+  typedef c4d acc;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef c4f acc;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+
+constexpr int NB = 16;            // block rows / panel columns
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+constexpr int64_t kMaxGrid = int64_t(1) << 22;   // workgroups per launch
+
+// This wave's share of C[i][j] = sum_{k0 <= k < k1} A(i, k) B(k, j), 0 <= i, j < 16:
+// 4-wide k steps go round robin to the NW waves.  a(i, k) and b(k, j) are only
+// called for k0 <= k < k1 and return zero outside the matrices.  Full waves only.
+template <typename Real, typename FA, typename FB>
+__device__ __forceinline__ typename Mfma<Real>::acc wave_gemm(FA a, FB b, int64_t k0, int64_t k1, int wv, int lane) {
+  typedef Mfma<Real> M;
+  typename M::acc c = {0, 0, 0, 0};
+  const int i = lane & 15, kk = lane >> 4;
+  constexpr int64_t step = 4 * NW;
+  int64_t kb = k0 + 4 * wv;
+  for (; kb + 3 * step < k1; kb += 4 * step) {   // four steps, loads first
+    Real av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = kb + u * step + kk;
+      const bool ok = k < k1;
+      av[u] = ok ? a(i, k) : Real(0);
+      bv[u] = ok ? b(k, i) : Real(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c = M::mac(av[u], bv[u], c);
+  }
+  for (; kb < k1; kb += step) {
+    const int64_t k = kb + kk;
+    const bool ok = k < k1;
+    c = M::mac(ok ? a(i, k) : Real(0), ok ? b(k, i) : Real(0), c);
+  }
+  return c;
+}
+
+template <typename Real>
+__device__ __forceinline__ void spill(const typename Mfma<Real>::acc& c, Real* red, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[Mfma<Real>::row(g, r) * NB + j] = c[r];
+}
+
+// Packed 'U' column pointer.
+__device__ __forceinline__ int64_t colp(int64_t j) { return j * (j + 1) / 2; }
+
+// Substitution with a 16 x 16 triangular block, one right-hand side per lane.
+// The unknowns still to be found sit in registers in the order they are
+// reached: each step takes v[0], removes it from the rest and shifts them down
+// one register, so every register index is static while the step k stays a
+// loop counter (a fully unrolled substitution would hold all 136 block entries
+// in registers).  t(k, m) is the coefficient linking the unknown of step k to
+// the one m steps later (t(k, 0) the pivot); put(k, x) receives the unknown of
+// step k.
+template <typename Real, typename FT, typename FP>
+__device__ __forceinline__ void substitute(Real (&v)[NB], FT t, FP put) {
+#pragma unroll 1
+  for (int k = 0; k < NB; ++k) {
+    const Real x = v[0] / t(k, 0);
+    put(k, x);
+#pragma unroll
+    for (int m = 1; m < NB; ++m) v[m - 1] = v[m] - t(k, m) * x;
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, int64_t n_elem,
+                                              int32_t* __restrict__ info) {
+  __shared__ Real s_red[NW][NB * NB];
+  __shared__ Real s_S[NB][NB + 1];
+  __shared__ Real s_T[NB][2 * NB];          // U[ib + r][ib + c] at [r][c]; columns >= NB zero
+  __shared__ int s_fail;
+  const int64_t e = blockIdx.x;
+  if (e >= n_elem) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  Real* a = ap + e * (n * (n + 1) / 2);
+  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
+
+  for (int64_t jb = 0; jb < n; jb += NB) {
+    const int w = int(std::min<int64_t>(NB, n - jb));
+    // Rows above the diagonal block, 16 at a time: U[Ib, P] = U[Ib, Ib]^{-T} (G[Ib, P] - U[:ib, Ib]^T U[:ib, P]).
+    for (int64_t ib = 0; ib < jb; ib += NB) {
+      const auto c = wave_gemm<Real>([&](int i, int64_t k) { return a[colp(ib + i) + k]; },
+                                     [&](int64_t k, int j) { return j < w ? a[colp(jb + j) + k] : Real(0); },
+                                     0, ib, wv, lane);
+      spill<Real>(c, s_red[wv], lane);
+      {
+        const int r = tid & 15, cc = tid >> 4;
+        s_T[r][cc] = r <= cc ? a[colp(ib + cc) + ib + r] : Real(0);
+      }
+      __syncthreads();
+      {
+        const int i = tid >> 4, j = tid & 15;
+        Real s = j < w ? a[colp(jb + j) + ib + i] : Real(0);
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
+        s_S[i][j] = s;
+      }
+      __syncthreads();
+      if (tid < NB) {                       // U[Ib, Ib]^T x = s, one column per lane
+        const int j = tid;
+        Real v[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
+        Real* dst = a + colp(jb + j) + ib;
+        substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k, Real x) {
+          if (j < w) dst[k] = x;
+        });
+      }
+      __syncthreads();
+    }
+    // Diagonal block: factor G[P, P] - U[:jb, P]^T U[:jb, P].
+    {
+      const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < w ? a[colp(jb + i) + k] : Real(0); },
+                                     [&](int64_t k, int j) { return j < w ? a[colp(jb + j) + k] : Real(0); },
+                                     0, jb, wv, lane);
+      spill<Real>(c, s_red[wv], lane);
+    }
+    __syncthreads();
+    {
+      const int i = tid >> 4, j = tid & 15;
+      Real s = (i <= j && j < w) ? a[colp(jb + j) + jb + i] : Real(0);
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
+      s_S[i][j] = s;
+    }
+    __syncthreads();
+    if (tid < NB) {                         // unblocked Cholesky, one column per lane
+      const int j = tid;
+      Real cl[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) cl[i] = s_S[i][j];
+      int fail = 0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (k < w && !fail) {               // uniform: w and the pivot are the same in every lane
+          const Real d = __shfl(cl[k], k);
+          if (!(d > Real(0))) {
+            fail = k + 1;
+          } else {
+            const Real ukk = sqrt(d);
+            cl[k] = j == k ? ukk : cl[k] / ukk;   // row k of U
+#pragma unroll
+            for (int i = k + 1; i < NB; ++i) cl[i] -= __shfl(cl[k], i) * cl[k];
+          }
+        }
+      }
+      if (j < w && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
+        Real* dst = a + colp(jb + j) + jb;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i <= j) dst[i] = cl[i];
+      }
+      if (j == 0) s_fail = fail ? int(jb) + fail : 0;
+    }
+    __syncthreads();
+    if (s_fail) {
+      if (tid == 0 && info) info[e] = s_fail;
+      return;
+    }
+  }
+  if (tid == 0 && info) info[e] = 0;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64_t n, int64_t n_elem, int64_t nrhs,
+                                              int64_t e0, Real* __restrict__ b) {
+  __shared__ Real s_red[NW][NB * NB];
+  __shared__ Real s_S[NB][NB + 1];
+  __shared__ Real s_T[NB][2 * NB];          // forward: U[ib + r][ib + c] at [r][c]; backward: at [c][NB - 1 - r]
+  const int64_t nblk = (nrhs + NB - 1) / NB;
+  const int64_t e = e0 + int64_t(blockIdx.x) / nblk, cb = int64_t(blockIdx.x) % nblk;
+  if (e >= n_elem) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const Real* u = up + e * (n * (n + 1) / 2);
+  Real* x = b + e * n * nrhs + cb * NB * n;        // column j of this block at x + j n
+  const int wc = int(std::min<int64_t>(NB, nrhs - cb * NB));
+  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
+
+  // The 16 x 16 diagonal block U[ib + r][ib + c] (rows and columns past n the identity).
+  auto load_t = [&](int64_t ib, int h, bool fwd) {
+    const int r = tid & 15, c = tid >> 4;
+    const Real t = (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
+    if (fwd)
+      s_T[r][c] = t;
+    else
+      s_T[c][NB - 1 - r] = t;
+  };
+  auto combine = [&](int64_t ib, int h) {
+    const int i = tid >> 4, j = tid & 15;
+    Real s = (i < h && j < wc) ? x[j * n + ib + i] : Real(0);
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
+    s_S[i][j] = s;
+  };
+
+  // U^T y = b, top down.
+  for (int64_t ib = 0; ib < n; ib += NB) {
+    const int h = int(std::min<int64_t>(NB, n - ib));
+    const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(ib + i) + k] : Real(0); },
+                                   [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
+                                   0, ib, wv, lane);
+    spill<Real>(c, s_red[wv], lane);
+    load_t(ib, h, true);
+    __syncthreads();
+    combine(ib, h);
+    __syncthreads();
+    if (tid < NB) {                         // U[Ib, Ib]^T y = s, rows top down
+      const int j = tid;
+      Real v[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
+      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k, Real y) {
+        if (j < wc && k < h) x[j * n + ib + k] = y;
+      });
+    }
+    __syncthreads();
+  }
+  // U x = y, bottom up.
+  for (int64_t ib = ((n - 1) / NB) * NB; ib >= 0; ib -= NB) {
+    const int h = int(std::min<int64_t>(NB, n - ib));
+    const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(k) + ib + i] : Real(0); },
+                                   [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
+                                   ib + h, n, wv, lane);
+    spill<Real>(c, s_red[wv], lane);
+    load_t(ib, h, false);
+    __syncthreads();
+    combine(ib, h);
+    __syncthreads();
+    if (tid < NB) {                         // U[Ib, Ib] x = s, step k is row NB - 1 - k
+      const int j = tid;
+      Real v[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v[r] = s_S[NB - 1 - r][j];
+      // U[NB-1-k-m][NB-1-k] sits at s_T[NB-1-k][k+m]
+      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; }, [&](int k, Real y) {
+        const int r = NB - 1 - k;
+        if (j < wc && r < h) x[j * n + ib + r] = y;
+      });
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_potrf(int prec, void* ap, int64_t n, int64_t n_elem, int32_t* info, hipStream_t st) {
+  const int64_t len = n * (n + 1) / 2;
+  for (int64_t e0 = 0; e0 < n_elem; e0 += kMaxGrid) {
+    const int64_t ne = std::min(kMaxGrid, n_elem - e0);
+    int32_t* inf = info ? info + e0 : nullptr;
+    if (prec)
+      hipLaunchKernelGGL(k_potrf<float>, dim3(unsigned(ne)), dim3(NT), 0, st, static_cast<float*>(ap) + e0 * len, n,
+                         ne, inf);
+    else
+      hipLaunchKernelGGL(k_potrf<double>, dim3(unsigned(ne)), dim3(NT), 0, st, static_cast<double*>(ap) + e0 * len,
+                         n, ne, inf);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_potrs(int prec, const void* up, int64_t n, int64_t n_elem, int64_t nrhs, void* b, hipStream_t st) {
+  const int64_t nblk = (nrhs + NB - 1) / NB;
+  const int64_t per = std::max<int64_t>(1, kMaxGrid / nblk);     // elements per launch
+  for (int64_t e0 = 0; e0 < n_elem; e0 += per) {
+    const int64_t ne = std::min(per, n_elem - e0);
+    const unsigned grid = unsigned(ne * nblk);
+    if (prec)
+      hipLaunchKernelGGL(k_potrs<float>, dim3(grid), dim3(NT), 0, st, static_cast<const float*>(up), n, e0 + ne,
+                         nrhs, e0, static_cast<float*>(b));
+    else
+      hipLaunchKernelGGL(k_potrs<double>, dim3(grid), dim3(NT), 0, st, static_cast<const double*>(up), n, e0 + ne,
+                         nrhs, e0, static_cast<double*>(b));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dpg

@@ -98,6 +98,10 @@ _lib.dpg_adjoint_coupling.argtypes = [_vp, _i, _vp, _i, _vp]
 _lib.dpg_adjoint_coupling.restype = _i
 _lib.dpg_replicate_blocks.argtypes = [_vp, _i64, _i64, _i, _vp, _vp, _i, _vp]
 _lib.dpg_replicate_blocks.restype = _i
+_lib.dpg_cholesky_packed.argtypes = [_vp, _i64, _i64, _vp, _vp, _i, _vp]
+_lib.dpg_cholesky_packed.restype = _i
+_lib.dpg_cholesky_solve_packed.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i, _vp]
+_lib.dpg_cholesky_solve_packed.restype = _i
 _lib.dpg_tune_save.argtypes = [_vp, ctypes.c_char_p]
 _lib.dpg_tune_save.restype = _i
 _lib.dpg_tune_load.argtypes = [_vp, ctypes.c_char_p]
@@ -315,6 +319,37 @@ class Context:
         _check(_lib.dpg_replicate_blocks(self._h, ne, n, copies, src.data_ptr(), out.data_ptr(), pr,
                                          _stream_ptr(stream)))
         return out
+
+    def cholesky(self, ap, n, info=None, stream=None):
+        """Cholesky factors of packed Grams of dimension n, in place
+        (dpg_cholesky_packed); ap is a float64 or float32 CUDA tensor holding
+        n_elem packed Grams, info an optional int32 CUDA tensor [n_elem]."""
+        m = n * (n + 1) // 2
+        if n < 1 or ap.numel() % m:
+            raise ValueError(f"size {ap.numel()} is not a multiple of the packed length {m}")
+        ne = ap.numel() // m
+        if info is not None and not (info.is_cuda and info.dtype == torch.int32 and info.numel() == ne):
+            raise ValueError("info must be an int32 CUDA tensor with one word per element")
+        pr = FP64 if ap.dtype == torch.float64 else FP32
+        _check(_lib.dpg_cholesky_packed(self._h, ne, n, ap.data_ptr(), None if info is None else info.data_ptr(),
+                                        pr, _stream_ptr(stream)))
+        return ap
+
+    def cholesky_solve(self, up, n, b, stream=None):
+        """b <- G^{-1} b per element (dpg_cholesky_solve_packed); up holds the
+        packed factors, b the n_elem column-major n x nrhs blocks (a tensor of
+        shape [n_elem, nrhs, n] is that layout)."""
+        m = n * (n + 1) // 2
+        if n < 1 or up.numel() % m:
+            raise ValueError(f"size {up.numel()} is not a multiple of the packed length {m}")
+        ne = up.numel() // m
+        if b.dtype != up.dtype or (ne and b.numel() % (ne * n)):
+            raise ValueError("right-hand sides must match the factor's dtype and hold n x nrhs per element")
+        nrhs = b.numel() // (ne * n) if ne else 1
+        pr = FP64 if up.dtype == torch.float64 else FP32
+        _check(_lib.dpg_cholesky_solve_packed(self._h, ne, n, up.data_ptr(), nrhs, b.data_ptr(), pr,
+                                              _stream_ptr(stream)))
+        return b
 
     def gram_batched(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
                      w0=1.0, w1=1.0, status=None, stream=None):
