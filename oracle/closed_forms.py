@@ -87,14 +87,19 @@ def F_table(r, s, nmax):
 # constant-Jacobian Kronecker form
 # ----------------------------------------------------------------------------
 
+def _orders(p):
+    return (int(p),) * 3 if np.ndim(p) == 0 else tuple(int(x) for x in p)
+
+
 def _ranges(space, p):
+    q = _orders(p)
     if space == "H1":
-        return [[p + 1] * 3]
+        return [[q[d] + 1 for d in range(3)]]
     if space == "L2":
-        return [[p] * 3]
+        return [[q[d] for d in range(3)]]
     if space == "HDIV":
-        return [[p + 1 if d == a else p for d in range(3)] for a in range(3)]
-    return [[p if d == a else p + 1 for d in range(3)] for a in range(3)]
+        return [[q[d] + 1 if d == a else q[d] for d in range(3)] for a in range(3)]
+    return [[q[d] if d == a else q[d] + 1 for d in range(3)] for a in range(3)]
 
 
 def _shift(space, a, d):
@@ -149,7 +154,8 @@ def block_terms(space, a, b, det, D, C, w0, w1):
 
 
 def kron_gram(space, p, J, w0=1, w1=1):
-    """Gram of an element with constant Jacobian J (3x3 nested lists or array).
+    """Gram of an element with constant Jacobian J (3x3 nested lists or array);
+    p is one order or three (p1, p2, p3), direction d taking its own range.
 
     Entries are Fractions when J, w0, w1 are Fractions/ints, floats otherwise.
     Returns an object array (exact) or float64 array.
@@ -164,7 +170,7 @@ def kron_gram(space, p, J, w0=1, w1=1):
     D = [[sum(Jinv[i][k] * Jinv[j][k] for k in range(3)) for j in range(3)] for i in range(3)]
     C = [[sum(J[k][i] * J[k][j] for k in range(3)) for j in range(3)] for i in range(3)]
     R = _ranges(space, p)
-    nmax = p + 1
+    nmax = max(_orders(p)) + 1
     Ft = {rs: F_table(rs[0], rs[1], nmax) for rs in _F}
     if not exact:
         Ft = {k: v.astype(np.float64) for k, v in Ft.items()}

@@ -29,16 +29,30 @@ import numpy as np
 from . import poly1d
 
 
+def orders(p):
+    """(p1, p2, p3) of an order given as one int (the same in every direction)
+    or per direction (the non-uniform orders of the text after Algorithm 2):
+    the 1D pair of direction d is (W_I^{p_d}, Y_I^{p_d}), so each formula below
+    takes p_d in direction d."""
+    if np.ndim(p) == 0:
+        return (int(p),) * 3
+    q = tuple(int(x) for x in p)
+    if len(q) != 3:
+        raise ValueError(f"need three orders, got {p}")
+    return q
+
+
 def ranges(space, p):
     """R[a][d]: number of 1D functions of direction d in component a."""
+    q = orders(p)
     if space == "H1":
-        return [[p + 1] * 3]
+        return [[q[d] + 1 for d in range(3)]]
     if space == "L2":
-        return [[p] * 3]
+        return [[q[d] for d in range(3)]]
     if space == "HDIV":
-        return [[p + 1 if d == a else p for d in range(3)] for a in range(3)]
+        return [[q[d] + 1 if d == a else q[d] for d in range(3)] for a in range(3)]
     if space == "HCURL":
-        return [[p if d == a else p + 1 for d in range(3)] for a in range(3)]
+        return [[q[d] if d == a else q[d] + 1 for d in range(3)] for a in range(3)]
     raise ValueError(space)
 
 
@@ -89,7 +103,7 @@ def evaluate(space, p, xi, subset=None):
     if subset is not None:
         idx = idx[np.asarray(subset, dtype=np.int64)]
     kinds = factor_kinds(space)
-    nmax = p + 1
+    nmax = max(orders(p)) + 1
     tab = {}
     for d in range(3):
         x = xi[:, d]
