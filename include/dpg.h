@@ -158,6 +158,21 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
                                const dpg_geometry* geom, const int64_t* out_offset, void* out,
                                const dpg_opts* opts, void* stream);
 
+/* Non-uniform orders (p1, p2, p3) (text after Algorithm 2): the 1D pair of
+ * direction d has order p[d] (device-independent host array int32[3], each in
+ * [1, 8]), so component a spans R_d(a) functions in direction d: H1 p_d+1;
+ * L2 p_d; H(div) p_d+1 if d = a else p_d; H(curl) p_d if d = a else p_d+1,
+ * flat index as for uniform orders (i1 fastest, components in order).  Each
+ * coordinate takes its own Gauss rule (p_d + 1 points, p_d for L2), or opts->nq
+ * points in every direction when nq > 0 (at most 9); the direction of least
+ * order is contracted last, in the outermost loop.  Output, geometry, status,
+ * weights and precision as for dpg_gram_integrate, with packed length
+ * n (n+1)/2, n = dpg_gram_dim_aniso(space, p).  Quadrature path only
+ * (DPG_PATH_REDUCED is rejected).  Errors: DPG_EINVAL, DPG_ENOTINIT, DPG_EHIP. */
+int64_t dpg_gram_dim_aniso(int space, const int32_t* p);
+int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
+                             const dpg_opts* opts, void* stream);
+
 /* Coupling block of the adjoint graph inner product of the ultraweak
  * formulation (Section 3.3, (3.17), (3.18)), whose test space is H1 x H(div):
  *   C[I][J] = int_K (v_J . grad q_I - q_I div v_J) dx,  q_I in W^p, v_J in V^p.

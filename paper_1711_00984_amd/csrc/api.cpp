@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "aniso.h"
 #include "condense.h"
 #include "ctx.h"
 #include "tables.h"
@@ -261,6 +262,62 @@ int dpg_cholesky_solve_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, con
   if (u0 < b1 && b0 < u1) return fail(DPG_EINVAL, "factor and right-hand side overlap");
   const hipError_t e = dpg::launch_potrs(prec, up, n, n_elem, nrhs, b, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? DPG_OK : hip_fail(e, "cholesky solve launch");
+}
+
+int64_t dpg_gram_dim_aniso(int space, const int32_t* p) {
+  if (!dpg::valid_space(space) || !p) return -1;
+  int64_t n = 0;
+  for (int d = 0; d < 3; ++d)
+    if (p[d] < 1 || p[d] > dpg::ANISO_PMAX) return -1;
+  for (int a = 0; a < (space == DPG_H1 || space == DPG_L2 ? 1 : 3); ++a) {
+    int64_t c = 1;
+    for (int d = 0; d < 3; ++d) {
+      const int q = p[d];
+      c *= space == DPG_H1 ? q + 1 : space == DPG_L2 ? q : space == DPG_HDIV ? (d == a ? q + 1 : q) : (d == a ? q : q + 1);
+    }
+    n += c;
+  }
+  return n;
+}
+
+int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
+                             const dpg_opts* opts, void* stream) {
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  int rc = dpg::check_common(ctx, geom, out, o);
+  if (rc) return rc;
+  if (!dpg::valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
+  if (!p) return fail(DPG_EINVAL, "orders are NULL");
+  for (int d = 0; d < 3; ++d)
+    if (p[d] < 1 || p[d] > dpg::ANISO_PMAX)
+      return fail(DPG_EINVAL, "p[%d]=%d outside [1, %d]", d, p[d], dpg::ANISO_PMAX);
+  if (o.path == DPG_PATH_REDUCED) return fail(DPG_EINVAL, "non-uniform orders use the quadrature path only");
+  if (o.nq < 0 || o.nq > dpg::ANISO_LMAX) return fail(DPG_EINVAL, "nq=%d outside [0, %d]", o.nq, dpg::ANISO_LMAX);
+  if (geom->n_elem == 0) return DPG_OK;
+  dpg::AnisoArgs a{};
+  a.geom = geom->data;
+  a.geom_kind = geom->kind;
+  a.n_elem = geom->n_elem;
+  a.out = out;
+  const int64_t n = dpg_gram_dim_aniso(space, p);
+  a.packed_len = n * (n + 1) / 2;
+  a.space = space;
+  for (int d = 0; d < 3; ++d) {
+    a.q[d] = p[d];
+    a.L[d] = o.nq > 0 ? o.nq : (space == DPG_L2 ? p[d] : p[d] + 1);
+    a.tab64[d] = ctx->d_tab64 + dpg::table_offset(a.L[d]);
+    a.tabR[d] = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + dpg::table_offset(a.L[d]))
+                                   : static_cast<const void*>(ctx->d_tab64 + dpg::table_offset(a.L[d]));
+  }
+  // contraction order: most points first, least last (outermost); ties keep xi3, xi2, xi1
+  int dir[3] = {2, 1, 0};
+  std::stable_sort(dir, dir + 3, [&](int x, int y) { return a.L[x] > a.L[y]; });
+  for (int k = 0; k < 3; ++k) a.dir[k] = dir[k];
+  a.w0 = o.w0;
+  a.w1 = o.w1;
+  a.status = o.status;
+  const hipError_t e = dpg::launch_aniso(o.prec, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPG_OK : hip_fail(e, "anisotropic launch");
 }
 
 }  // extern "C"

@@ -1,0 +1,298 @@
+// gram_aniso.hip -- element Grams of non-uniform orders (p1, p2, p3).
+//
+// When the orders differ per direction, each coordinate can take its own 1D
+// Gauss rule (L_d = p_d + 1 points, p_d for L2), and the nesting of the staged
+// quadrature should put the coordinate of least order in the outermost loop
+// (text after Algorithm 2): the last contraction costs L_out times the number
+// of entries, so L_out should be the smallest.  The directions are therefore
+// contracted in the order dir[0] (the largest order), dir[1], dir[2] (the
+// least), with the terms of Sections 2.3-2.6 (the same integrands as the
+// uniform kernels; component a of a space spans R_d(a) functions in direction
+// d, from p_d).
+//
+// One workgroup per (element, component block a <= b), FP64 or FP32 VALU:
+//   fields  c_t at all L1 L2 L3 points (FP64 metric, times the weights) -> LDS
+//   for each pair (iA, jA) of the first direction:
+//     stage A: A_g[qC][qB]             = sum_qA c_t T_A T_A            (terms -> groups g)
+//     stage B: B_h[qC][iB][jB]         = sum_qB T_B T_B A_g            (groups -> groups h)
+//     stage C: G[(iA,iB,iC),(jA,jB,jC)] = sum_h sum_qC T_C T_C B_h     -> packed 'U' output
+// Terms sharing their derivative flags in directions B and C share stages B
+// and C; groups sharing them in direction C share stage C.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "aniso.h"
+#include "kernels.h"
+#include "metric.h"
+#include "terms.h"
+
+namespace dpg {
+
+namespace {
+
+constexpr int NTA = 256;
+constexpr int MT = 10;                                      // terms per block (H1)
+constexpr int MF = 7;                                       // distinct fields per block (H1)
+constexpr int MH = 4;                                       // stage-C groups
+constexpr int QMAX = ANISO_LMAX * ANISO_LMAX * ANISO_LMAX;
+constexpr int TSTRIDE = ANISO_LMAX;                         // table row length in LDS
+constexpr int TDIR = 2 * KT * TSTRIDE;                      // one direction: chi then chi'
+constexpr int64_t kMaxGrid = int64_t(1) << 22;
+
+struct Meta {
+  int nt, nf, ng, nh;
+  int fid[MF];          // metric field of each distinct field
+  int tf[MT];           // term -> distinct field
+  double coef[MT];      // term sign times w0 or w1
+  int r[MT][3], s[MT][3];
+  int tg[MT];           // term -> stage-A group
+  int gr[MT][3], gs[MT][3];   // flags of each stage-A group (directions B and C meaningful)
+  int gh[MT];           // stage-A group -> stage-C group
+  int hr[MH], hs[MH];   // flags of each stage-C group in direction C
+};
+
+__device__ __forceinline__ int shift_of(int space, int a, int d) {
+  return space == SP_H1 ? 0 : space == SP_L2 ? 1 : space == SP_HDIV ? (d == a ? 0 : 1) : (d == a ? 1 : 0);
+}
+__device__ __forceinline__ int range_of(int space, const int* q, int a, int d) {
+  return space == SP_H1 ? q[d] + 1 : space == SP_L2 ? q[d] : space == SP_HDIV ? (d == a ? q[d] + 1 : q[d])
+                                                                               : (d == a ? q[d] : q[d] + 1);
+}
+
+// Terms of block (a, b) (the integrands listed in terms.h), their fields and groups.
+__device__ void build_meta(int space, int a, int b, double w0, double w1, const int* dir, Meta& m) {
+  m.nt = 0;
+  auto add = [&](int f, double c, int ra, int rb) {   // ra / rb: direction whose flag is set (-1: none, 3: all)
+    const int t = m.nt++;
+    m.tf[t] = f;
+    m.coef[t] = c;
+    for (int d = 0; d < 3; ++d) {
+      m.r[t][d] = ra == 3 ? 1 : (d == ra ? 1 : 0);
+      m.s[t][d] = rb == 3 ? 1 : (d == rb ? 1 : 0);
+    }
+  };
+  auto add_co = [&](int f, double c, int ca, int cb) {  // flags 1 - e_ca, 1 - e_cb
+    const int t = m.nt++;
+    m.tf[t] = f;
+    m.coef[t] = c;
+    for (int d = 0; d < 3; ++d) {
+      m.r[t][d] = d == ca ? 0 : 1;
+      m.s[t][d] = d == cb ? 0 : 1;
+    }
+  };
+  if (space == SP_H1) {
+    add(FLD_DETJ, w0, -1, -1);
+    for (int A = 0; A < 3; ++A)
+      for (int B = 0; B < 3; ++B) add(fld_D(A, B), w1, A, B);
+  } else if (space == SP_L2) {
+    add(FLD_IDETJ, w0, 3, 3);
+  } else if (space == SP_HDIV) {
+    add_co(fld_C(a, b), w0, a, b);
+    add(FLD_IDETJ, w1, 3, 3);
+  } else {
+    add(fld_D(a, b), w0, a, b);
+    for (int al = 1; al <= 2; ++al)
+      for (int be = 1; be <= 2; ++be) {
+        const int ca = (a + al) % 3, cb = (b + be) % 3;
+        add_co(fld_C(ca, cb), ((al + be) & 1) ? -w1 : w1, ca, cb);
+      }
+  }
+  // distinct fields
+  m.nf = 0;
+  for (int t = 0; t < m.nt; ++t) {
+    int k = 0;
+    while (k < m.nf && m.fid[k] != m.tf[t]) ++k;
+    if (k == m.nf) m.fid[m.nf++] = m.tf[t];
+    m.tf[t] = k;
+  }
+  const int dB = dir[1], dC = dir[2];
+  // stage-A groups: same flags in directions B and C
+  m.ng = 0;
+  for (int t = 0; t < m.nt; ++t) {
+    int g = 0;
+    while (g < m.ng && !(m.gr[g][dB] == m.r[t][dB] && m.gs[g][dB] == m.s[t][dB] && m.gr[g][dC] == m.r[t][dC] &&
+                         m.gs[g][dC] == m.s[t][dC]))
+      ++g;
+    if (g == m.ng) {
+      for (int d = 0; d < 3; ++d) {
+        m.gr[g][d] = m.r[t][d];
+        m.gs[g][d] = m.s[t][d];
+      }
+      ++m.ng;
+    }
+    m.tg[t] = g;
+  }
+  // stage-C groups: same flags in direction C
+  m.nh = 0;
+  for (int g = 0; g < m.ng; ++g) {
+    int h = 0;
+    while (h < m.nh && !(m.hr[h] == m.gr[g][dC] && m.hs[h] == m.gs[g][dC])) ++h;
+    if (h == m.nh) {
+      m.hr[h] = m.gr[g][dC];
+      m.hs[h] = m.gs[g][dC];
+      ++m.nh;
+    }
+    m.gh[g] = h;
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t item0) {
+  __shared__ Real s_tab[3 * TDIR];          // direction d: chi^<r>_k(zeta_l) at d TDIR + r KT TSTRIDE + k TSTRIDE + l
+  __shared__ Real s_F[MF * QMAX];           // fields, point q = qA + LA (qB + LB qC)
+  __shared__ Real s_A[MT * ANISO_LMAX * ANISO_LMAX];
+  __shared__ Real s_B[MH * ANISO_LMAX * ANISO_LMAX * ANISO_LMAX];
+  __shared__ Meta m;
+  __shared__ int s_bad;
+
+  const int64_t item = item0 + blockIdx.x;
+  const int64_t e = item / nblk;
+  if (e >= A.n_elem) return;
+  int blk = int(item % nblk), a = 0, b = 0;
+  while (blk >= 3 - a) {                    // (a, b), a <= b, in the order (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+    blk -= 3 - a;
+    ++a;
+  }
+  b = a + blk;
+  const int tid = threadIdx.x;
+  const int sp = A.space;
+  const int dA = A.dir[0], dB = A.dir[1], dC = A.dir[2];
+  const int LA = A.L[dA], LB = A.L[dB], LC = A.L[dC];
+  const int Q = LA * LB * LC;
+
+  if (tid == 0) {
+    build_meta(sp, a, b, A.w0, A.w1, A.dir, m);
+    s_bad = 0;
+  }
+  for (int k = tid; k < 3 * TDIR; k += NTA) {
+    const int d = k / TDIR, rem = k % TDIR, r = rem / (KT * TSTRIDE), kk = (rem / TSTRIDE) % KT, l = rem % TSTRIDE;
+    const int L = A.L[d];
+    const Real* t = static_cast<const Real*>(A.tabR[d]);
+    s_tab[k] = l < L ? t[2 * L + (r * KT + kk) * L + l] : Real(0);
+  }
+  __syncthreads();
+
+  // metric fields, weighted
+  const double* X = A.geom + e * geom_stride(A.geom_kind);
+  for (int q = tid; q < Q; q += NTA) {
+    const int qA = q % LA, qB = (q / LA) % LB, qC = q / (LA * LB);
+    int qd[3];
+    qd[dA] = qA;
+    qd[dB] = qB;
+    qd[dC] = qC;
+    double xi[3], w = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      xi[d] = A.tab64[d][qd[d]];
+      w *= A.tab64[d][A.L[d] + qd[d]];
+    }
+    double J[3][3], adj[3][3];
+    jacobian_at(A.geom_kind, X, xi[0], xi[1], xi[2], J);
+    const double det = adjugate(J, adj);
+    if (!(det > 0.0)) s_bad = 1;
+    const double idet = 1.0 / det;
+    for (int f = 0; f < m.nf; ++f) s_F[f * Q + q] = Real(field_value(m.fid[f], J, adj, det, idet) * w);
+  }
+  __syncthreads();
+
+  int Ra[3], Rb[3], sa[3], sb[3];
+  for (int d = 0; d < 3; ++d) {
+    Ra[d] = range_of(sp, A.q, a, d);
+    Rb[d] = range_of(sp, A.q, b, d);
+    sa[d] = shift_of(sp, a, d);
+    sb[d] = shift_of(sp, b, d);
+  }
+  int offa = 0, offb = 0;
+  for (int c = 0; c < b; ++c) {
+    const int nc = range_of(sp, A.q, c, 0) * range_of(sp, A.q, c, 1) * range_of(sp, A.q, c, 2);
+    if (c < a) offa += nc;
+    offb += nc;
+  }
+  Real* out = static_cast<Real*>(A.out) + e * A.packed_len;
+  const int nB = Ra[dB] * Rb[dB], nC = Ra[dC] * Rb[dC];
+  auto entry = [&](int iA, int jA, int iB, int jB, int iC, int jC, int64_t& I, int64_t& J) {
+    int i[3], j[3];
+    i[dA] = iA; i[dB] = iB; i[dC] = iC;
+    j[dA] = jA; j[dB] = jB; j[dC] = jC;
+    I = offa + i[0] + Ra[0] * (i[1] + Ra[1] * i[2]);
+    J = offb + j[0] + Rb[0] * (j[1] + Rb[1] * j[2]);
+  };
+
+  if (s_bad) {                              // det J <= 0 somewhere: zero this block, flag the element
+    const int64_t na = int64_t(Ra[0]) * Ra[1] * Ra[2], nb = int64_t(Rb[0]) * Rb[1] * Rb[2];
+    for (int64_t k = tid; k < na * nb; k += NTA) {
+      const int64_t I = offa + k % na, J = offb + k / na;
+      if (a != b || I <= J) out[I + J * (J + 1) / 2] = Real(0);
+    }
+    if (tid == 0 && A.status) A.status[e] = -4;
+    return;
+  }
+  if (tid == 0 && A.status && a == 0 && b == 0) A.status[e] = 0;
+
+  auto tab = [&](int d, int r, int k, int l) { return s_tab[d * TDIR + (r * KT + k) * TSTRIDE + l]; };
+
+  for (int iA = 0; iA < Ra[dA]; ++iA)
+    for (int jA = 0; jA < Rb[dA]; ++jA) {
+      // stage A: contract the first direction
+      for (int o = tid; o < m.ng * LC * LB; o += NTA) {
+        const int g = o / (LC * LB), qC = (o / LB) % LC, qB = o % LB;
+        Real v = 0;
+        for (int t = 0; t < m.nt; ++t) {
+          if (m.tg[t] != g) continue;
+          const Real* f = s_F + m.tf[t] * Q + LA * (qB + LB * qC);
+          Real u = 0;
+          for (int qA = 0; qA < LA; ++qA)
+            u += f[qA] * tab(dA, m.r[t][dA], iA + sa[dA], qA) * tab(dA, m.s[t][dA], jA + sb[dA], qA);
+          v += Real(m.coef[t]) * u;
+        }
+        s_A[o] = v;
+      }
+      __syncthreads();
+      // stage B: contract the second direction
+      for (int o = tid; o < m.nh * LC * nB; o += NTA) {
+        const int h = o / (LC * nB), qC = (o / nB) % LC, ij = o % nB, iB = ij / Rb[dB], jB = ij % Rb[dB];
+        Real v = 0;
+        for (int g = 0; g < m.ng; ++g) {
+          if (m.gh[g] != h) continue;
+          const Real* x = s_A + (g * LC + qC) * LB;
+          for (int qB = 0; qB < LB; ++qB)
+            v += x[qB] * tab(dB, m.gr[g][dB], iB + sa[dB], qB) * tab(dB, m.gs[g][dB], jB + sb[dB], qB);
+        }
+        s_B[o] = v;
+      }
+      __syncthreads();
+      // stage C: contract the last direction (least order) and store
+      for (int o = tid; o < nC * nB; o += NTA) {
+        const int ij = o % nB, iB = ij / Rb[dB], jB = ij % Rb[dB];
+        const int ijC = o / nB, iC = ijC / Rb[dC], jC = ijC % Rb[dC];
+        int64_t I, J;
+        entry(iA, jA, iB, jB, iC, jC, I, J);
+        if (a == b && I > J) continue;
+        Real v = 0;
+        for (int h = 0; h < m.nh; ++h) {
+          const Real* x = s_B + h * LC * nB + ij;
+          for (int qC = 0; qC < LC; ++qC)
+            v += x[qC * nB] * tab(dC, m.hr[h], iC + sa[dC], qC) * tab(dC, m.hs[h], jC + sb[dC], qC);
+        }
+        out[I + J * (J + 1) / 2] = v;
+      }
+      __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_aniso(int prec, const AnisoArgs& a, hipStream_t st) {
+  const int nblk = (a.space == SP_H1 || a.space == SP_L2) ? 1 : 6;
+  const int64_t items = a.n_elem * nblk;
+  for (int64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
+    const unsigned grid = unsigned(std::min(kMaxGrid, items - i0));
+    if (prec)
+      hipLaunchKernelGGL(k_aniso<float>, dim3(grid), dim3(NTA), 0, st, a, nblk, i0);
+    else
+      hipLaunchKernelGGL(k_aniso<double>, dim3(grid), dim3(NTA), 0, st, a, nblk, i0);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dpg

@@ -98,6 +98,10 @@ _lib.dpg_adjoint_coupling.argtypes = [_vp, _i, _vp, _i, _vp]
 _lib.dpg_adjoint_coupling.restype = _i
 _lib.dpg_replicate_blocks.argtypes = [_vp, _i64, _i64, _i, _vp, _vp, _i, _vp]
 _lib.dpg_replicate_blocks.restype = _i
+_lib.dpg_gram_dim_aniso.argtypes = [_i, _vp]
+_lib.dpg_gram_dim_aniso.restype = _i64
+_lib.dpg_gram_integrate_aniso.argtypes = [_vp, _i, _vp, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp]
+_lib.dpg_gram_integrate_aniso.restype = _i
 _lib.dpg_cholesky_packed.argtypes = [_vp, _i64, _i64, _vp, _vp, _i, _vp]
 _lib.dpg_cholesky_packed.restype = _i
 _lib.dpg_cholesky_solve_packed.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i, _vp]
@@ -162,6 +166,18 @@ def gram_dim(space, p):
 
 def packed_len(space, p):
     return int(_lib.dpg_gram_packed_len(space_id(space), p))
+
+
+def _orders(p):
+    q = (ctypes.c_int32 * 3)(*[int(x) for x in p])
+    if len(p) != 3:
+        raise ValueError("need three orders")
+    return q
+
+
+def gram_dim_aniso(space, p):
+    """Dimension of `space` with orders p = (p1, p2, p3) (dpg_gram_dim_aniso)."""
+    return int(_lib.dpg_gram_dim_aniso(space_id(space), _orders(p)))
 
 
 def general_flops(space, p):
@@ -318,6 +334,24 @@ class Context:
             out = torch.empty(ne * (cn * (cn + 1) // 2), dtype=src.dtype, device="cuda")
         _check(_lib.dpg_replicate_blocks(self._h, ne, n, copies, src.data_ptr(), out.data_ptr(), pr,
                                          _stream_ptr(stream)))
+        return out
+
+    def gram_aniso(self, space, p, geom, kind="trilinear", out=None, prec="fp64", nq=0, w0=1.0, w1=1.0,
+                   status=None, stream=None):
+        """Packed Grams of non-uniform orders p = (p1, p2, p3) (dpg_gram_integrate_aniso)."""
+        g = _geometry(geom, kind)
+        dt = torch.float64 if prec in ("fp64", FP64) else torch.float32
+        nd = gram_dim_aniso(space, p)
+        if nd < 0:
+            raise DpgError(EINVAL, f"invalid space/orders ({space}, {tuple(p)})")
+        n = g.n_elem * (nd * (nd + 1) // 2)
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=geom.device)
+        elif out.dtype != dt or out.numel() < n or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype or size")
+        o = _opts(prec, "auto", nq, w0, w1, status)
+        _check(_lib.dpg_gram_integrate_aniso(self._h, space_id(space), _orders(p), ctypes.byref(g),
+                                             out.data_ptr(), ctypes.byref(o), _stream_ptr(stream)))
         return out
 
     def cholesky(self, ap, n, info=None, stream=None):

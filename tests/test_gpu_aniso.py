@@ -1,0 +1,161 @@
+"""GPU parity of the Grams of non-uniform orders (p1, p2, p3) (the text after
+Algorithm 2: one Gauss rule per coordinate, least-order coordinate
+outermost) against the FP64 oracle, through the C ABI.
+
+Tolerances as for the uniform kernels: FP64 1e-12 (relative Frobenius and
+max), FP32 2e-6 (relative Frobenius); both sides use the same per-direction
+rules, so they differ by rounding only.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+from oracle import gram as og
+from oracle import shapes
+
+pytestmark = pytest.mark.gpu
+
+SPACES = ["H1", "HCURL", "HDIV", "L2"]
+TOL64 = 1e-12
+FP32_REL = 2e-6
+
+
+def say(*a):
+    print("[gpu-aniso]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dpg():
+    from tests._lib import load_binding
+    return load_binding()
+
+
+@pytest.fixture(scope="module")
+def ctx(dpg):
+    c = dpg.Context(p_max=11)
+    yield c
+    c.close()
+
+
+def run(ctx, space, q, geom, kind="trilinear", prec="fp64", nq=0, status=None):
+    g = torch.from_numpy(np.ascontiguousarray(geom)).cuda()
+    out = ctx.gram_aniso(space, q, g, kind=kind, prec=prec, nq=nq, status=status)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def elem(o, e, space, q):
+    n = shapes.dimension(space, q)
+    m = n * (n + 1) // 2
+    return og.unpack_upper(o[e * m:(e + 1) * m].astype(np.float64), n)
+
+
+def rel(G, R):
+    return np.linalg.norm(G - R) / np.linalg.norm(R), np.abs(G - R).max() / np.abs(R).max()
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("q", [(1, 2, 3), (3, 1, 2), (2, 4, 1), (1, 1, 1), (3, 3, 2)])
+def test_aniso_vs_oracle(ctx, space, q):
+    say(space, q)
+    E = 3
+    X = meshgen.perturbed_hexes(E, seed=600 + sum(q))
+    o64 = run(ctx, space, q, X)
+    o32 = run(ctx, space, q, X, prec="fp32")
+    for e in range(E):
+        R = og.gram(space, q, "trilinear", X[e])
+        fro, mx = rel(elem(o64, e, space, q), R)
+        assert fro <= TOL64 and mx <= TOL64, f"{space} {q} e={e}: fro {fro:.3e} max {mx:.3e}"
+        fro32, _ = rel(elem(o32, e, space, q), R)
+        assert fro32 <= FP32_REL, f"{space} {q} e={e} fp32: {fro32:.3e}"
+
+
+@pytest.mark.parametrize("space,q", [("H1", (8, 5, 7)), ("HCURL", (6, 4, 5)), ("HDIV", (4, 6, 5)), ("L2", (8, 7, 6))])
+def test_aniso_high_orders(ctx, space, q):
+    say("high", space, q)
+    X = meshgen.perturbed_hexes(2, seed=610)
+    o = run(ctx, space, q, X)
+    for e in range(2):
+        R = og.gram(space, q, "trilinear", X[e])
+        fro, mx = rel(elem(o, e, space, q), R)
+        assert fro <= TOL64 and mx <= TOL64, f"{space} {q} e={e}: fro {fro:.3e} max {mx:.3e}"
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [2, 5])
+def test_uniform_orders_match_the_uniform_kernels(ctx, space, p):
+    X = meshgen.perturbed_hexes(4, seed=620 + p)
+    a = run(ctx, space, (p, p, p), X)
+    u = ctx.gram(space, p, torch.from_numpy(X).cuda()).cpu().numpy()
+    for e in range(4):
+        fro, mx = rel(elem(a, e, space, (p,) * 3), elem(u, e, space, (p,) * 3))
+        assert fro <= TOL64 and mx <= TOL64, f"{space} p={p} e={e}"
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_one_rule_for_all_directions(ctx, space):
+    """nq > 0: the same nq-point rule in every direction (the shortcut of
+    using the largest rule everywhere)."""
+    q = (2, 4, 3)
+    X = meshgen.perturbed_hexes(2, seed=630)
+    o = run(ctx, space, q, X, nq=6)
+    for e in range(2):
+        R = og.gram(space, q, "trilinear", X[e], L=6)
+        fro, mx = rel(elem(o, e, space, q), R)
+        assert fro <= TOL64 and mx <= TOL64, f"{space} e={e}"
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_affine_and_extruded_geometry(ctx, space):
+    q = (3, 2, 4)
+    A = meshgen.affine_parallelepipeds(2, seed=640)
+    o = run(ctx, space, q, A, kind="affine")
+    for e in range(2):
+        fro, mx = rel(elem(o, e, space, q), og.gram(space, q, "affine", A[e]))
+        assert fro <= TOL64 and mx <= TOL64
+    Ex = meshgen.extruded_prisms(2, seed=641)
+    o = run(ctx, space, q, Ex, kind="extruded")
+    T = meshgen.extruded_as_trilinear(Ex)
+    for e in range(2):
+        fro, mx = rel(elem(o, e, space, q), og.gram(space, q, "trilinear", T[e]))
+        assert fro <= TOL64 and mx <= TOL64
+
+
+def test_cyclic_relabelling(ctx):
+    """Relabelling (xi1, xi2, xi3) -> (xi2, xi3, xi1) in the map and the orders
+    permutes the H1 basis, which changes the contraction order chosen for the
+    least-order direction; the GPU results must agree after renumbering."""
+    q = (2, 5, 3)
+    qs = (q[1], q[2], q[0])
+    X = meshgen.perturbed_hexes(1, seed=650)[0]
+    perm = [((v >> 2) & 1) | ((v & 1) << 1) | (((v >> 1) & 1) << 2) for v in range(8)]
+    G = elem(run(ctx, "H1", q, X[None]), 0, "H1", q)
+    Gs = elem(run(ctx, "H1", qs, X[perm][None]), 0, "H1", qs)
+    R1, R2, R3 = q[0] + 1, q[1] + 1, q[2] + 1
+    idx = [i2 + R2 * i3 + R2 * R3 * i1 for i3 in range(R3) for i2 in range(R2) for i1 in range(R1)]
+    fro, mx = rel(Gs[np.ix_(idx, idx)], G)
+    assert fro <= TOL64 and mx <= TOL64
+
+
+def test_bad_element_empty_and_errors(ctx, dpg):
+    q = (2, 3, 1)
+    X = meshgen.perturbed_hexes(3, seed=660)
+    X[1] = X[1][[1, 0, 2, 3, 4, 5, 6, 7]]                  # swap two vertices: det J < 0 somewhere
+    st = torch.full((3,), 7, dtype=torch.int32, device="cuda")
+    for space in ("H1", "HDIV"):
+        o = run(ctx, space, q, X, status=st)
+        assert list(st.cpu().numpy()) == [0, dpg.EJACOBIAN, 0]
+        m = dpg.gram_dim_aniso(space, q)
+        m = m * (m + 1) // 2
+        assert np.all(o[m:2 * m] == 0)
+        fro, _ = rel(elem(o, 2, space, q), og.gram(space, q, "trilinear", X[2]))
+        assert fro <= TOL64
+    empty = torch.empty((0,), dtype=torch.float64, device="cuda")
+    assert ctx.gram_aniso("H1", q, empty).numel() == 0
+    g = torch.from_numpy(meshgen.perturbed_hexes(1, seed=661)).cuda()
+    for bad in ((0, 1, 1), (1, 9, 1)):
+        with pytest.raises(dpg.DpgError):
+            ctx.gram_aniso("H1", bad, g)
+    with pytest.raises(dpg.DpgError):
+        ctx.gram_aniso("H1", q, g, nq=10)
