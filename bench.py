@@ -294,6 +294,29 @@ def run_extra(ctx, dpg, stream, E, X, out64):
                                  "hbm_frac": round(moved / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     log(f"[bench] extra replicate {res['replicate_h1_p7_x3']}")
     del src, dst
+    # non-uniform orders (p1, p2, p3): one rule per coordinate, least order outermost; the same
+    # elements at (7, 7, 7) through the uniform kernel for comparison
+    ani = []
+    for space, q in (("H1", (7, 6, 5)), ("H1", (7, 7, 7)), ("HCURL", (6, 5, 4)), ("HDIV", (5, 6, 4))):
+        nd = dpg.gram_dim_aniso(space, q)
+        mm = nd * (nd + 1) // 2
+        n_a = int(min(4096, (2 << 30) // (mm * 8)))
+        Xa = torch.from_numpy(meshgen.perturbed_hexes(n_a, noise=0.15, seed=1712)).cuda()
+        o = torch.empty(n_a * mm, dtype=torch.float64, device="cuda")
+        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, stream=stream), 3, 1, stream)
+        kk = float(np.mean(pr))
+        row = {"space": space, "p": list(q), "n_elem": n_a, "kernel_ms": round(kk, 3),
+               "elements_per_s": round(n_a / (kk * 1e-3), 1),
+               "hbm_gbs": round(mm * 8 * n_a / (kk * 1e-3) / 1e9, 1)}
+        if len(set(q)) == 1:
+            w, pr = time_launches(lambda: ctx.gram(space, q[0], Xa, out=o, stream=stream), 3, 1, stream)
+            row["uniform_kernel_ms"] = round(float(np.mean(pr)), 3)
+        ani.append(row)
+        log(f"[bench] extra aniso {row}")
+        del o, Xa
+        torch.cuda.empty_cache()
+    res["aniso_orders"] = ani
+
     # static condensation on the device: Cholesky factor of the benchmark's Grams in place, then
     # G^{-1} B for 343 right-hand sides (the H1 trial space of order 6 of the Poisson example)
     n_c, sp_c, p_c, nrhs_c = 1024, "H1", 7, 343

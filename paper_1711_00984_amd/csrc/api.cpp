@@ -309,10 +309,16 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
     a.tabR[d] = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + dpg::table_offset(a.L[d]))
                                    : static_cast<const void*>(ctx->d_tab64 + dpg::table_offset(a.L[d]));
   }
-  // contraction order: most points first, least last (outermost); ties keep xi3, xi2, xi1
-  int dir[3] = {2, 1, 0};
-  std::stable_sort(dir, dir + 3, [&](int x, int y) { return a.L[x] > a.L[y]; });
-  for (int k = 0; k < 3; ++k) a.dir[k] = dir[k];
+  // Contraction order: the direction with the fewest points last (outermost loop; ties
+  // go to the lowest direction, so uniform orders keep xi3, xi2, xi1).  Of the other two,
+  // xi3 (the slowest index of the flat numbering) goes first when it is among them, which
+  // lets a diagonal block skip the pairs i3 > j3.
+  int dC = 0;
+  for (int d = 1; d < 3; ++d)
+    if (a.L[d] < a.L[dC]) dC = d;
+  a.dir[0] = dC == 2 ? 1 : 2;
+  a.dir[1] = 3 - dC - a.dir[0];
+  a.dir[2] = dC;
   a.w0 = o.w0;
   a.w1 = o.w1;
   a.status = o.status;

@@ -5,16 +5,19 @@
 // quadrature should put the coordinate of least order in the outermost loop
 // (text after Algorithm 2): the last contraction costs L_out times the number
 // of entries, so L_out should be the smallest.  The directions are therefore
-// contracted in the order dir[0] (the largest order), dir[1], dir[2] (the
-// least), with the terms of Sections 2.3-2.6 (the same integrands as the
+// contracted in the order dir[0], dir[1], dir[2] (the least order).  dir[0] is
+// xi3, the slowest index of the flat numbering, whenever xi3 is not the least
+// order, so that a diagonal block can skip the pairs i3 > j3 whole; otherwise
+// the last stage skips them.  The integrands are the terms of
+// Sections 2.3-2.6 (the same integrands as the
 // uniform kernels; component a of a space spans R_d(a) functions in direction
 // d, from p_d).
 //
 // One workgroup per (element, component block a <= b), FP64 or FP32 VALU:
 //   fields  c_t at all L1 L2 L3 points (FP64 metric, times the weights) -> LDS
-//   for each pair (iA, jA) of the first direction:
+//   for each pair (iA, jA) of the first direction (several at once for small blocks):
 //     stage A: A_g[qC][qB]             = sum_qA c_t T_A T_A            (terms -> groups g)
-//     stage B: B_h[qC][iB][jB]         = sum_qB T_B T_B A_g            (groups -> groups h)
+//     stage B: B_h[qC][jB][iB]         = sum_qB T_B T_B A_g            (groups -> groups h)
 //     stage C: G[(iA,iB,iC),(jA,jB,jC)] = sum_h sum_qC T_C T_C B_h     -> packed 'U' output
 // Terms sharing their derivative flags in directions B and C share stages B
 // and C; groups sharing them in direction C share stage C.
@@ -209,7 +212,7 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
     offb += nc;
   }
   Real* out = static_cast<Real*>(A.out) + e * A.packed_len;
-  const int nB = Ra[dB] * Rb[dB], nC = Ra[dC] * Rb[dC];
+  const int nB = Ra[dB] * Rb[dB];
   auto entry = [&](int iA, int jA, int iB, int jB, int iC, int jC, int64_t& I, int64_t& J) {
     int i[3], j[3];
     i[dA] = iA; i[dB] = iB; i[dC] = iC;
@@ -231,53 +234,120 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
 
   auto tab = [&](int d, int r, int k, int l) { return s_tab[d * TDIR + (r * KT + k) * TSTRIDE + l]; };
 
-  for (int iA = 0; iA < Ra[dA]; ++iA)
-    for (int jA = 0; jA < Rb[dA]; ++jA) {
-      // stage A: contract the first direction
-      for (int o = tid; o < m.ng * LC * LB; o += NTA) {
-        const int g = o / (LC * LB), qC = (o / LB) % LC, qB = o % LB;
-        Real v = 0;
-        for (int t = 0; t < m.nt; ++t) {
-          if (m.tg[t] != g) continue;
-          const Real* f = s_F + m.tf[t] * Q + LA * (qB + LB * qC);
-          Real u = 0;
-          for (int qA = 0; qA < LA; ++qA)
-            u += f[qA] * tab(dA, m.r[t][dA], iA + sa[dA], qA) * tab(dA, m.s[t][dA], jA + sb[dA], qA);
-          v += Real(m.coef[t]) * u;
-        }
-        s_A[o] = v;
+  const int RaB = Ra[dB], RaC = Ra[dC], RbC = Rb[dC];
+  // Pairs (iA, jA) still to do (a diagonal block with xi3 first skips i3 > j3), taken P
+  // at a time when the stage buffers hold P pairs' intermediates: small blocks would
+  // otherwise leave most threads idle between two barriers.
+  const int nAs = m.ng * LC * LB, nBs = m.nh * LC * nB;
+  const int P = max(1, min(min(int(sizeof(s_A) / sizeof(Real)) / nAs, int(sizeof(s_B) / sizeof(Real)) / nBs), 16));
+  __shared__ int s_pair[ANISO_LMAX * ANISO_LMAX];
+  __shared__ int s_npair;
+  if (tid == 0) {
+    int np = 0;
+    for (int iA = 0; iA < Ra[dA]; ++iA)
+      for (int jA = 0; jA < Rb[dA]; ++jA)
+        if (!(a == b && dA == 2 && iA > jA)) s_pair[np++] = iA * ANISO_LMAX + jA;
+    s_npair = np;
+  }
+  __syncthreads();
+  const int ncI = (RaC + 1) / 2, ncJ = (RbC + 1) / 2, nq4 = (nB + 3) / 4, nCt = nq4 * ncI * ncJ;
+  for (int p0 = 0; p0 < s_npair; p0 += P) {
+    const int np = min(P, s_npair - p0);
+    // stage A: contract the first direction
+    for (int o = tid; o < np * nAs; o += NTA) {
+      const int pp = o / nAs, oo = o % nAs;
+      const int iA = s_pair[p0 + pp] / ANISO_LMAX, jA = s_pair[p0 + pp] % ANISO_LMAX;
+      const int g = oo / (LC * LB), qC = (oo / LB) % LC, qB = oo % LB;
+      Real v = 0;
+      for (int t = 0; t < m.nt; ++t) {
+        if (m.tg[t] != g) continue;
+        const Real* f = s_F + m.tf[t] * Q + LA * (qB + LB * qC);
+        Real u = 0;
+        for (int qA = 0; qA < LA; ++qA)
+          u += f[qA] * tab(dA, m.r[t][dA], iA + sa[dA], qA) * tab(dA, m.s[t][dA], jA + sb[dA], qA);
+        v += Real(m.coef[t]) * u;
       }
-      __syncthreads();
-      // stage B: contract the second direction
-      for (int o = tid; o < m.nh * LC * nB; o += NTA) {
-        const int h = o / (LC * nB), qC = (o / nB) % LC, ij = o % nB, iB = ij / Rb[dB], jB = ij % Rb[dB];
-        Real v = 0;
-        for (int g = 0; g < m.ng; ++g) {
-          if (m.gh[g] != h) continue;
-          const Real* x = s_A + (g * LC + qC) * LB;
-          for (int qB = 0; qB < LB; ++qB)
-            v += x[qB] * tab(dB, m.gr[g][dB], iB + sa[dB], qB) * tab(dB, m.gs[g][dB], jB + sb[dB], qB);
-        }
-        s_B[o] = v;
-      }
-      __syncthreads();
-      // stage C: contract the last direction (least order) and store
-      for (int o = tid; o < nC * nB; o += NTA) {
-        const int ij = o % nB, iB = ij / Rb[dB], jB = ij % Rb[dB];
-        const int ijC = o / nB, iC = ijC / Rb[dC], jC = ijC % Rb[dC];
-        int64_t I, J;
-        entry(iA, jA, iB, jB, iC, jC, I, J);
-        if (a == b && I > J) continue;
-        Real v = 0;
-        for (int h = 0; h < m.nh; ++h) {
-          const Real* x = s_B + h * LC * nB + ij;
-          for (int qC = 0; qC < LC; ++qC)
-            v += x[qC * nB] * tab(dC, m.hr[h], iC + sa[dC], qC) * tab(dC, m.hs[h], jC + sb[dC], qC);
-        }
-        out[I + J * (J + 1) / 2] = v;
-      }
-      __syncthreads();
+      s_A[o] = v;
     }
+    __syncthreads();
+    // stage B: contract the second direction, B_h[qC][jB][iB]; one thread per (h, iB, jB)
+    // keeps all qC in registers, and A_g is the same for every lane (broadcast reads)
+    for (int o = tid; o < np * m.nh * nB; o += NTA) {
+      const int pp = o / (m.nh * nB), oo = o % (m.nh * nB);
+      const int h = oo / nB, ij = oo % nB, iB = ij % RaB, jB = ij / RaB;
+      Real acc[ANISO_LMAX];
+#pragma unroll
+      for (int c = 0; c < ANISO_LMAX; ++c) acc[c] = 0;
+      for (int g = 0; g < m.ng; ++g) {
+        if (m.gh[g] != h) continue;
+        const int rg = m.gr[g][dB], sg = m.gs[g][dB];
+        const Real* x = s_A + pp * nAs + g * LC * LB;
+        for (int qB = 0; qB < LB; ++qB) {
+          const Real pq = tab(dB, rg, iB + sa[dB], qB) * tab(dB, sg, jB + sb[dB], qB);
+#pragma unroll
+          for (int c = 0; c < ANISO_LMAX; ++c)
+            if (c < LC) acc[c] += pq * x[c * LB + qB];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < ANISO_LMAX; ++c)
+        if (c < LC) s_B[pp * nBs + (h * LC + c) * nB + ij] = acc[c];
+    }
+    __syncthreads();
+    // stage C: contract the last direction (least order) and store.  One thread per
+    // 2 x 2 block of (iC, jC) and 4 consecutive (iB, jB): per point four B values and
+    // four table values feed sixteen multiply-adds.  With xi3 contracted here, a
+    // diagonal block skips the (iC, jC) blocks that lie wholly below the diagonal.
+    for (int o = tid; o < np * nCt; o += NTA) {
+      const int pp = o / nCt, oo = o % nCt;
+      const int iA = s_pair[p0 + pp] / ANISO_LMAX, jA = s_pair[p0 + pp] % ANISO_LMAX;
+      const int ij0 = 4 * (oo % nq4), ch = oo / nq4, ci = 2 * (ch % ncI), cj = 2 * (ch / ncI);
+      if (a == b && dC == 2 && ci > cj + 1) continue;
+      Real acc[2][2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) acc[u][v][w] = 0;
+      for (int h = 0; h < m.nh; ++h) {
+        const int rh = m.hr[h], sh = m.hs[h];
+        const Real* x = s_B + pp * nBs + h * LC * nB;
+        for (int qC = 0; qC < LC; ++qC) {
+          Real xv[4], pr[2][2];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) xv[w] = ij0 + w < nB ? x[qC * nB + ij0 + w] : Real(0);
+          // rows / columns past the range repeat the last one (not stored)
+          const Real ti0 = tab(dC, rh, ci + sa[dC], qC), ti1 = tab(dC, rh, min(ci + 1, RaC - 1) + sa[dC], qC);
+          const Real tj0 = tab(dC, sh, cj + sb[dC], qC), tj1 = tab(dC, sh, min(cj + 1, RbC - 1) + sb[dC], qC);
+          pr[0][0] = ti0 * tj0;
+          pr[0][1] = ti0 * tj1;
+          pr[1][0] = ti1 * tj0;
+          pr[1][1] = ti1 * tj1;
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+              for (int w = 0; w < 4; ++w) acc[u][v][w] += pr[u][v] * xv[w];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int iC = ci + u, jC = cj + v, ij = ij0 + w;
+            if (iC < RaC && jC < RbC && ij < nB) {
+              int64_t I, J;
+              entry(iA, jA, ij % RaB, ij / RaB, iC, jC, I, J);
+              if (a != b || I <= J) out[I + J * (J + 1) / 2] = acc[u][v][w];
+            }
+          }
+    }
+    __syncthreads();
+  }
 }
 
 }  // namespace
