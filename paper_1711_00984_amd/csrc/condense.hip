@@ -98,13 +98,13 @@ __device__ __forceinline__ int64_t colp(int64_t j) { return j * (j + 1) / 2; }
 // one register, so every register index is static while the step k stays a
 // loop counter (a fully unrolled substitution would hold all 136 block entries
 // in registers).  t(k, m) is the coefficient linking the unknown of step k to
-// the one m steps later (t(k, 0) the pivot); put(k, x) receives the unknown of
-// step k.
-template <typename Real, typename FT, typename FP>
-__device__ __forceinline__ void substitute(Real (&v)[NB], FT t, FP put) {
+// the one m steps later, rpiv(k) the reciprocal of the pivot t(k, 0) (computed once
+// per block, so a step costs one multiply); put(k, x) receives the unknown of step k.
+template <typename Real, typename FT, typename FR, typename FP>
+__device__ __forceinline__ void substitute(Real (&v)[NB], FT t, FR rpiv, FP put) {
 #pragma unroll 1
   for (int k = 0; k < NB; ++k) {
-    const Real x = v[0] / t(k, 0);
+    const Real x = v[0] * rpiv(k);
     put(k, x);
 #pragma unroll
     for (int m = 1; m < NB; ++m) v[m - 1] = v[m] - t(k, m) * x;
@@ -117,6 +117,7 @@ __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, 
   __shared__ Real s_red[NW][NB * NB];
   __shared__ Real s_S[NB][NB + 1];
   __shared__ Real s_T[NB][2 * NB];          // U[ib + r][ib + c] at [r][c]; columns >= NB zero
+  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r]
   __shared__ int s_fail;
   const int64_t e = blockIdx.x;
   if (e >= n_elem) return;
@@ -128,21 +129,23 @@ __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, 
     const int w = int(std::min<int64_t>(NB, n - jb));
     // Rows above the diagonal block, 16 at a time: U[Ib, P] = U[Ib, Ib]^{-T} (G[Ib, P] - U[:ib, Ib]^T U[:ib, P]).
     for (int64_t ib = 0; ib < jb; ib += NB) {
+      // this thread's entries of the Gram block and of the diagonal block, fetched
+      // before the contraction so that their latency overlaps it
+      const int gi = tid >> 4, gj = tid & 15, tr = tid & 15, tc = tid >> 4;
+      const Real gv = gj < w ? a[colp(jb + gj) + ib + gi] : Real(0);
+      const Real tv = tr <= tc ? a[colp(ib + tc) + ib + tr] : Real(0);
       const auto c = wave_gemm<Real>([&](int i, int64_t k) { return a[colp(ib + i) + k]; },
                                      [&](int64_t k, int j) { return j < w ? a[colp(jb + j) + k] : Real(0); },
                                      0, ib, wv, lane);
       spill<Real>(c, s_red[wv], lane);
-      {
-        const int r = tid & 15, cc = tid >> 4;
-        s_T[r][cc] = r <= cc ? a[colp(ib + cc) + ib + r] : Real(0);
-      }
+      s_T[tr][tc] = tv;
+      if (tr == tc) s_rd[tr] = Real(1) / tv;
       __syncthreads();
       {
-        const int i = tid >> 4, j = tid & 15;
-        Real s = j < w ? a[colp(jb + j) + ib + i] : Real(0);
+        Real s = gv;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
-        s_S[i][j] = s;
+        for (int q = 0; q < NW; ++q) s -= s_red[q][gi * NB + gj];
+        s_S[gi][gj] = s;
       }
       __syncthreads();
       if (tid < NB) {                       // U[Ib, Ib]^T x = s, one column per lane
@@ -151,9 +154,10 @@ __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, 
 #pragma unroll
         for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
         Real* dst = a + colp(jb + j) + ib;
-        substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k, Real x) {
-          if (j < w) dst[k] = x;
-        });
+        substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
+                         [&](int k, Real x) {
+                           if (j < w) dst[k] = x;
+                         });
       }
       __syncthreads();
     }
@@ -216,6 +220,7 @@ __global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64
   __shared__ Real s_red[NW][NB * NB];
   __shared__ Real s_S[NB][NB + 1];
   __shared__ Real s_T[NB][2 * NB];          // forward: U[ib + r][ib + c] at [r][c]; backward: at [c][NB - 1 - r]
+  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r] (rows past n: 1)
   const int64_t nblk = (nrhs + NB - 1) / NB;
   const int64_t e = e0 + int64_t(blockIdx.x) / nblk, cb = int64_t(blockIdx.x) % nblk;
   if (e >= n_elem) return;
@@ -226,17 +231,24 @@ __global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64
   s_T[tid >> 4][NB + (tid & 15)] = Real(0);
 
   // The 16 x 16 diagonal block U[ib + r][ib + c] (rows and columns past n the identity).
-  auto load_t = [&](int64_t ib, int h, bool fwd) {
+  auto fetch_t = [&](int64_t ib, int h) {
     const int r = tid & 15, c = tid >> 4;
-    const Real t = (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
+    return (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
+  };
+  auto put_t = [&](Real t, bool fwd) {
+    const int r = tid & 15, c = tid >> 4;
     if (fwd)
       s_T[r][c] = t;
     else
       s_T[c][NB - 1 - r] = t;
+    if (r == c) s_rd[r] = Real(1) / t;
   };
-  auto combine = [&](int64_t ib, int h) {
+  auto fetch_x = [&](int64_t ib, int h) {
     const int i = tid >> 4, j = tid & 15;
-    Real s = (i < h && j < wc) ? x[j * n + ib + i] : Real(0);
+    return (i < h && j < wc) ? x[j * n + ib + i] : Real(0);
+  };
+  auto combine = [&](Real s) {
+    const int i = tid >> 4, j = tid & 15;
 #pragma unroll
     for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
     s_S[i][j] = s;
@@ -245,35 +257,38 @@ __global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64
   // U^T y = b, top down.
   for (int64_t ib = 0; ib < n; ib += NB) {
     const int h = int(std::min<int64_t>(NB, n - ib));
+    const Real tv = fetch_t(ib, h), xv = fetch_x(ib, h);
     const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(ib + i) + k] : Real(0); },
                                    [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
                                    0, ib, wv, lane);
     spill<Real>(c, s_red[wv], lane);
-    load_t(ib, h, true);
+    put_t(tv, true);
     __syncthreads();
-    combine(ib, h);
+    combine(xv);
     __syncthreads();
     if (tid < NB) {                         // U[Ib, Ib]^T y = s, rows top down
       const int j = tid;
       Real v[NB];
 #pragma unroll
       for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
-      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k, Real y) {
-        if (j < wc && k < h) x[j * n + ib + k] = y;
-      });
+      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
+                       [&](int k, Real y) {
+                         if (j < wc && k < h) x[j * n + ib + k] = y;
+                       });
     }
     __syncthreads();
   }
   // U x = y, bottom up.
   for (int64_t ib = ((n - 1) / NB) * NB; ib >= 0; ib -= NB) {
     const int h = int(std::min<int64_t>(NB, n - ib));
+    const Real tv = fetch_t(ib, h), xv = fetch_x(ib, h);
     const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(k) + ib + i] : Real(0); },
                                    [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
                                    ib + h, n, wv, lane);
     spill<Real>(c, s_red[wv], lane);
-    load_t(ib, h, false);
+    put_t(tv, false);
     __syncthreads();
-    combine(ib, h);
+    combine(xv);
     __syncthreads();
     if (tid < NB) {                         // U[Ib, Ib] x = s, step k is row NB - 1 - k
       const int j = tid;
@@ -281,10 +296,11 @@ __global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64
 #pragma unroll
       for (int r = 0; r < NB; ++r) v[r] = s_S[NB - 1 - r][j];
       // U[NB-1-k-m][NB-1-k] sits at s_T[NB-1-k][k+m]
-      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; }, [&](int k, Real y) {
-        const int r = NB - 1 - k;
-        if (j < wc && r < h) x[j * n + ib + r] = y;
-      });
+      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; },
+                       [&](int k) { return s_rd[NB - 1 - k]; }, [&](int k, Real y) {
+                         const int r = NB - 1 - k;
+                         if (j < wc && r < h) x[j * n + ib + r] = y;
+                       });
     }
     __syncthreads();
   }
