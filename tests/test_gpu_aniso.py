@@ -159,3 +159,18 @@ def test_bad_element_empty_and_errors(ctx, dpg):
             ctx.gram_aniso("H1", bad, g)
     with pytest.raises(dpg.DpgError):
         ctx.gram_aniso("H1", q, g, nq=10)
+
+
+def test_benchmark_size_sampled(ctx, dpg):
+    """The launch the benchmark times for non-uniform orders: 4096 hexes, H1
+    (7, 6, 5); sampled elements against the oracle."""
+    q, E = (7, 6, 5), 4096
+    X = meshgen.perturbed_hexes(E, noise=0.15, seed=1712)
+    o = ctx.gram_aniso("H1", q, torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    n = dpg.gram_dim_aniso("H1", q)
+    m = n * (n + 1) // 2
+    for e in (0, 2049, E - 1):
+        G = og.unpack_upper(o[e * m:(e + 1) * m].cpu().numpy(), n)
+        fro, mx = rel(G, og.gram("H1", q, "trilinear", X[e]))
+        assert fro <= TOL64 and mx <= TOL64, (e, fro, mx)

@@ -199,3 +199,29 @@ def test_errors_and_empty(ctx, dpg):
     assert rc == dpg.EINVAL
     rc = dpg._lib.dpg_cholesky_packed(ctx.handle, 1, n, ap.data_ptr(), None, 7, None)
     assert rc == dpg.EINVAL
+
+
+def test_benchmark_size_sampled(ctx, dpg):
+    """The launch the benchmark times: 1024 H1 p = 7 Grams (n = 512) factored in
+    place, then G^-1 B with 343 right-hand sides; sampled elements against the
+    oracle."""
+    space, p, E, nrhs = "H1", 7, 1024, 343
+    n = dpg.gram_dim(space, p)
+    X = meshgen.perturbed_hexes(E, noise=0.15, seed=1713)
+    G = ctx.gram(space, p, torch.from_numpy(X).cuda())
+    m = n * (n + 1) // 2
+    picks = [0, 517, E - 1]
+    Gs = {e: G[e * m:(e + 1) * m].cpu().numpy() for e in picks}
+    info = torch.full((E,), -99, dtype=torch.int32, device="cuda")
+    ctx.cholesky(G, n, info=info)
+    B = torch.randn(E, nrhs, n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(11))
+    Bs = {e: B[e].cpu().numpy() for e in picks}
+    ctx.cholesky_solve(G, n, B)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    for e in picks:
+        Ge = og.unpack_upper(Gs[e], n)
+        check_factor(G[e * m:(e + 1) * m].cpu().numpy(), Ge, "fp64", f"benchmark e={e}")
+        R = condense.solve_packed(condense.cholesky_packed(Gs[e], n)[0], n, Bs[e].T)
+        err = np.abs(B[e].cpu().numpy().T - R).max() / np.abs(R).max()
+        assert err <= 8 * n * EPS["fp64"] * np.linalg.cond(Ge), (e, err)
