@@ -111,104 +111,135 @@ __device__ __forceinline__ void substitute(Real (&v)[NB], FT t, FR rpiv, FP put)
   }
 }
 
+// One wave's 16 x 16 x K contraction over contiguous columns, all k steps its own:
+// lane (i, kk) holds column i of A at pa and column i of B at pb (va, vb false: zero).
+template <typename Real>
+__device__ __forceinline__ typename Mfma<Real>::acc wave_gemm_own(const Real* pa, const Real* pb, bool va, bool vb,
+                                                                  int64_t k1, int lane) {
+  typedef Mfma<Real> M;
+  typename M::acc c = {0, 0, 0, 0};
+  const int kk = lane >> 4;
+  int64_t kb = 0;
+  for (; kb + 16 <= k1; kb += 16) {                // four steps, loads first
+    Real av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = va ? pa[kb + 4 * u + kk] : Real(0);
+      bv[u] = vb ? pb[kb + 4 * u + kk] : Real(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c = M::mac(av[u], bv[u], c);
+  }
+  for (; kb < k1; kb += 4) {
+    const int64_t k = kb + kk;
+    const bool ok = k < k1;
+    c = M::mac(ok && va ? pa[k] : Real(0), ok && vb ? pb[k] : Real(0), c);
+  }
+  return c;
+}
+
+// Panels of PW = 64 columns, one 16-column tile per wave.  For each 16-row block ib
+// down the panel, every wave whose tile lies on or right of the diagonal contracts
+// its own tile (no cross-wave sum): S = G[Ib, tile] - U[:ib, Ib]^T U[:ib, tile], with
+// the Gram entries fetched beforehand into the accumulator's own layout.  Above the
+// panel's diagonal block the tile is finished by substitution with U[Ib, Ib] (read
+// from memory); inside it, the wave holding the diagonal tile factors it first and the
+// waves to its right substitute with the new factor.  n / 16 (n / 64 + 1) / 2 row
+// blocks per element instead of n^2 / 512 with 16-column panels.
 template <typename Real>
 __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, int64_t n_elem,
                                               int32_t* __restrict__ info) {
-  __shared__ Real s_red[NW][NB * NB];
-  __shared__ Real s_S[NB][NB + 1];
+  typedef Mfma<Real> M;
+  constexpr int PW = NB * NW;
+  __shared__ Real s_S[NW][NB][NB + 1];      // each wave's tile, row-major
   __shared__ Real s_T[NB][2 * NB];          // U[ib + r][ib + c] at [r][c]; columns >= NB zero
   __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r]
   __shared__ int s_fail;
   const int64_t e = blockIdx.x;
   if (e >= n_elem) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
   Real* a = ap + e * (n * (n + 1) / 2);
   s_T[tid >> 4][NB + (tid & 15)] = Real(0);
 
-  for (int64_t jb = 0; jb < n; jb += NB) {
-    const int w = int(std::min<int64_t>(NB, n - jb));
-    // Rows above the diagonal block, 16 at a time: U[Ib, P] = U[Ib, Ib]^{-T} (G[Ib, P] - U[:ib, Ib]^T U[:ib, P]).
-    for (int64_t ib = 0; ib < jb; ib += NB) {
-      // this thread's entries of the Gram block and of the diagonal block, fetched
-      // before the contraction so that their latency overlaps it
-      const int gi = tid >> 4, gj = tid & 15, tr = tid & 15, tc = tid >> 4;
-      const Real gv = gj < w ? a[colp(jb + gj) + ib + gi] : Real(0);
-      const Real tv = tr <= tc ? a[colp(ib + tc) + ib + tr] : Real(0);
-      const auto c = wave_gemm<Real>([&](int i, int64_t k) { return a[colp(ib + i) + k]; },
-                                     [&](int64_t k, int j) { return j < w ? a[colp(jb + j) + k] : Real(0); },
-                                     0, ib, wv, lane);
-      spill<Real>(c, s_red[wv], lane);
-      s_T[tr][tc] = tv;
-      if (tr == tc) s_rd[tr] = Real(1) / tv;
-      __syncthreads();
-      {
-        Real s = gv;
+  for (int64_t jb = 0; jb < n; jb += PW) {
+    const int64_t c0 = jb + NB * wv;                         // this wave's first column
+    const int wc = int(std::max<int64_t>(0, std::min<int64_t>(NB, n - c0)));   // its columns (0: none)
+    const int64_t iend = std::min<int64_t>(jb + PW, n);
+    for (int64_t ib = 0; ib < iend; ib += NB) {
+      const bool inside = ib >= jb;                          // row block inside the panel's diagonal block
+      const int dw = inside ? int((ib - jb) / NB) : -1;      // wave holding the diagonal tile
+      const bool act = wc > 0 && c0 >= ib;
+      const bool dtile = act && c0 == ib;
+      // Gram entries of this lane's accumulator slots, and (above the diagonal block) one
+      // entry of U[Ib, Ib] per thread, fetched before the contraction
+      Real gv[4];
 #pragma unroll
-        for (int q = 0; q < NW; ++q) s -= s_red[q][gi * NB + gj];
-        s_S[gi][gj] = s;
+      for (int r = 0; r < 4; ++r) {
+        const int row = M::row(lg, r);
+        const bool ok = act && li < wc && (!dtile || row <= li);
+        gv[r] = ok ? a[colp(c0 + li) + ib + row] : Real(0);
+      }
+      const int tr = tid & 15, tc = tid >> 4;
+      const Real tv = (!inside && tr <= tc) ? a[colp(ib + tc) + ib + tr] : Real(0);
+      typename M::acc c = {0, 0, 0, 0};
+      if (act) c = wave_gemm_own<Real>(a + colp(ib + li), a + colp(c0 + li), ib + li < n, li < wc, ib, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s_S[wv][M::row(lg, r)][li] = gv[r] - c[r];
+      if (!inside) {
+        s_T[tr][tc] = tv;
+        if (tr == tc) s_rd[tr] = Real(1) / tv;
       }
       __syncthreads();
-      if (tid < NB) {                       // U[Ib, Ib]^T x = s, one column per lane
-        const int j = tid;
+      if (inside) {
+        if (dtile && lane < NB) {           // unblocked Cholesky of the diagonal tile, one column per lane
+          const int j = lane, w = wc;
+          Real cl[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) cl[i] = s_S[wv][i][j];
+          int fail = 0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) {
+            if (k < w && !fail) {           // uniform: w and the pivot are the same in every lane
+              const Real d = __shfl(cl[k], k);
+              if (!(d > Real(0))) {
+                fail = k + 1;
+              } else {
+                const Real ukk = sqrt(d);
+                cl[k] = j == k ? ukk : cl[k] / ukk;   // row k of U
+#pragma unroll
+                for (int i = k + 1; i < NB; ++i) cl[i] -= __shfl(cl[k], i) * cl[k];
+              }
+            }
+          }
+          if (j < w && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
+            Real* dst = a + colp(ib + j) + ib;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+              if (i <= j) dst[i] = cl[i];
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i) s_T[i][j] = i <= j ? cl[i] : Real(0);
+          s_rd[j] = j < w ? Real(1) / cl[j] : Real(1);
+          if (j == 0) s_fail = fail ? int(ib) + fail : 0;
+        }
+        __syncthreads();
+        if (s_fail) {
+          if (tid == 0 && info) info[e] = s_fail;
+          return;
+        }
+      }
+      if (act && !dtile && lane < NB) {     // U[Ib, Ib]^T x = s, one column of the tile per lane
+        const int j = lane;
         Real v[NB];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
-        Real* dst = a + colp(jb + j) + ib;
+        for (int r = 0; r < NB; ++r) v[r] = s_S[wv][r][j];
+        Real* dst = a + colp(c0 + j) + ib;
         substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
                          [&](int k, Real x) {
-                           if (j < w) dst[k] = x;
+                           if (j < wc) dst[k] = x;
                          });
       }
       __syncthreads();
-    }
-    // Diagonal block: factor G[P, P] - U[:jb, P]^T U[:jb, P].
-    {
-      const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < w ? a[colp(jb + i) + k] : Real(0); },
-                                     [&](int64_t k, int j) { return j < w ? a[colp(jb + j) + k] : Real(0); },
-                                     0, jb, wv, lane);
-      spill<Real>(c, s_red[wv], lane);
-    }
-    __syncthreads();
-    {
-      const int i = tid >> 4, j = tid & 15;
-      Real s = (i <= j && j < w) ? a[colp(jb + j) + jb + i] : Real(0);
-#pragma unroll
-      for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
-      s_S[i][j] = s;
-    }
-    __syncthreads();
-    if (tid < NB) {                         // unblocked Cholesky, one column per lane
-      const int j = tid;
-      Real cl[NB];
-#pragma unroll
-      for (int i = 0; i < NB; ++i) cl[i] = s_S[i][j];
-      int fail = 0;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        if (k < w && !fail) {               // uniform: w and the pivot are the same in every lane
-          const Real d = __shfl(cl[k], k);
-          if (!(d > Real(0))) {
-            fail = k + 1;
-          } else {
-            const Real ukk = sqrt(d);
-            cl[k] = j == k ? ukk : cl[k] / ukk;   // row k of U
-#pragma unroll
-            for (int i = k + 1; i < NB; ++i) cl[i] -= __shfl(cl[k], i) * cl[k];
-          }
-        }
-      }
-      if (j < w && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
-        Real* dst = a + colp(jb + j) + jb;
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-          if (i <= j) dst[i] = cl[i];
-      }
-      if (j == 0) s_fail = fail ? int(jb) + fail : 0;
-    }
-    __syncthreads();
-    if (s_fail) {
-      if (tid == 0 && info) info[e] = s_fail;
-      return;
     }
   }
   if (tid == 0 && info) info[e] = 0;
