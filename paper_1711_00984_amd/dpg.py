@@ -169,10 +169,16 @@ def packed_len(space, p):
 
 
 def _orders(p):
-    q = (ctypes.c_int32 * 3)(*[int(x) for x in p])
+    p = [int(x) for x in p]
     if len(p) != 3:
         raise ValueError("need three orders")
-    return q
+    return (ctypes.c_int32 * 3)(*p)
+
+
+def _dense(t, what):
+    if not (t.is_cuda and t.is_contiguous() and t.dtype in (torch.float64, torch.float32)):
+        raise ValueError(f"{what} must be a contiguous float64 or float32 CUDA tensor")
+    return FP64 if t.dtype == torch.float64 else FP32
 
 
 def gram_dim_aniso(space, p):
@@ -358,13 +364,13 @@ class Context:
         """Cholesky factors of packed Grams of dimension n, in place
         (dpg_cholesky_packed); ap is a float64 or float32 CUDA tensor holding
         n_elem packed Grams, info an optional int32 CUDA tensor [n_elem]."""
+        pr = _dense(ap, "packed Grams")
         m = n * (n + 1) // 2
         if n < 1 or ap.numel() % m:
             raise ValueError(f"size {ap.numel()} is not a multiple of the packed length {m}")
         ne = ap.numel() // m
         if info is not None and not (info.is_cuda and info.dtype == torch.int32 and info.numel() == ne):
             raise ValueError("info must be an int32 CUDA tensor with one word per element")
-        pr = FP64 if ap.dtype == torch.float64 else FP32
         _check(_lib.dpg_cholesky_packed(self._h, ne, n, ap.data_ptr(), None if info is None else info.data_ptr(),
                                         pr, _stream_ptr(stream)))
         return ap
@@ -373,6 +379,8 @@ class Context:
         """b <- G^{-1} b per element (dpg_cholesky_solve_packed); up holds the
         packed factors, b the n_elem column-major n x nrhs blocks (a tensor of
         shape [n_elem, nrhs, n] is that layout)."""
+        pr = _dense(up, "packed factors")
+        _dense(b, "right-hand sides")
         m = n * (n + 1) // 2
         if n < 1 or up.numel() % m:
             raise ValueError(f"size {up.numel()} is not a multiple of the packed length {m}")
@@ -380,7 +388,6 @@ class Context:
         if b.dtype != up.dtype or (ne and b.numel() % (ne * n)):
             raise ValueError("right-hand sides must match the factor's dtype and hold n x nrhs per element")
         nrhs = b.numel() // (ne * n) if ne else 1
-        pr = FP64 if up.dtype == torch.float64 else FP32
         _check(_lib.dpg_cholesky_solve_packed(self._h, ne, n, up.data_ptr(), nrhs, b.data_ptr(), pr,
                                               _stream_ptr(stream)))
         return b
