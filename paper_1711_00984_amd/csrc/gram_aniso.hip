@@ -282,11 +282,17 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
         if (m.gh[g] != h) continue;
         const int rg = m.gr[g][dB], sg = m.gs[g][dB];
         const Real* x = s_A + pp * nAs + g * LC * LB;
-        for (int qB = 0; qB < LB; ++qB) {
-          const Real pq = tab(dB, rg, iB + sa[dB], qB) * tab(dB, sg, jB + sb[dB], qB);
+        for (int q0 = 0; q0 < LB; q0 += 2) {   // two points per pass, their reads issued together
+          Real pq[2];
+          int qq[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            qq[t] = min(q0 + t, LB - 1);
+            pq[t] = q0 + t < LB ? tab(dB, rg, iB + sa[dB], qq[t]) * tab(dB, sg, jB + sb[dB], qq[t]) : Real(0);
+          }
 #pragma unroll
           for (int c = 0; c < ANISO_LMAX; ++c)
-            if (c < LC) acc[c] += pq * x[c * LB + qB];
+            if (c < LC) acc[c] += pq[0] * x[c * LB + qq[0]] + pq[1] * x[c * LB + qq[1]];
         }
       }
 #pragma unroll
@@ -313,23 +319,30 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
       for (int h = 0; h < m.nh; ++h) {
         const int rh = m.hr[h], sh = m.hs[h];
         const Real* x = s_B + pp * nBs + h * LC * nB;
-        for (int qC = 0; qC < LC; ++qC) {
-          Real xv[4], pr[2][2];
+        for (int q0 = 0; q0 < LC; q0 += 2) {   // two points per pass, their reads issued together
+          Real xv[2][4], pr[2][2][2];
 #pragma unroll
-          for (int w = 0; w < 4; ++w) xv[w] = ij0 + w < nB ? x[qC * nB + ij0 + w] : Real(0);
-          // rows / columns past the range repeat the last one (not stored)
-          const Real ti0 = tab(dC, rh, ci + sa[dC], qC), ti1 = tab(dC, rh, min(ci + 1, RaC - 1) + sa[dC], qC);
-          const Real tj0 = tab(dC, sh, cj + sb[dC], qC), tj1 = tab(dC, sh, min(cj + 1, RbC - 1) + sb[dC], qC);
-          pr[0][0] = ti0 * tj0;
-          pr[0][1] = ti0 * tj1;
-          pr[1][0] = ti1 * tj0;
-          pr[1][1] = ti1 * tj1;
+          for (int t = 0; t < 2; ++t) {
+            const int qC = min(q0 + t, LC - 1);
+            const bool live = q0 + t < LC;
 #pragma unroll
-          for (int u = 0; u < 2; ++u)
+            for (int w = 0; w < 4; ++w) xv[t][w] = live && ij0 + w < nB ? x[qC * nB + ij0 + w] : Real(0);
+            // rows / columns past the range repeat the last one (not stored)
+            const Real ti0 = tab(dC, rh, ci + sa[dC], qC), ti1 = tab(dC, rh, min(ci + 1, RaC - 1) + sa[dC], qC);
+            const Real tj0 = tab(dC, sh, cj + sb[dC], qC), tj1 = tab(dC, sh, min(cj + 1, RbC - 1) + sb[dC], qC);
+            pr[t][0][0] = ti0 * tj0;
+            pr[t][0][1] = ti0 * tj1;
+            pr[t][1][0] = ti1 * tj0;
+            pr[t][1][1] = ti1 * tj1;
+          }
 #pragma unroll
-            for (int v = 0; v < 2; ++v)
+          for (int t = 0; t < 2; ++t)
 #pragma unroll
-              for (int w = 0; w < 4; ++w) acc[u][v][w] += pr[u][v] * xv[w];
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+              for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc[u][v][w] += pr[t][u][v] * xv[t][w];
         }
       }
 #pragma unroll
