@@ -24,6 +24,9 @@ struct AnisoArgs {
   const void* tabR[3];     // the same blocks in the output precision
   double w0, w1;
   int32_t* status;         // per element (nullptr: none)
+  // set by the launcher: LDS sizes in Reals (fields; one pair's stage-A buffer) and
+  // the pairs per barrier interval
+  int lds_fields = 0, lds_a = 0, pairs = 1;
 };
 
 hipError_t launch_aniso(int prec, const AnisoArgs& a, hipStream_t s);

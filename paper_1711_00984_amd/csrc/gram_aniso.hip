@@ -38,7 +38,6 @@ constexpr int NTA = 256;
 constexpr int MT = 10;                                      // terms per block (H1)
 constexpr int MF = 7;                                       // distinct fields per block (H1)
 constexpr int MH = 4;                                       // stage-C groups
-constexpr int QMAX = ANISO_LMAX * ANISO_LMAX * ANISO_LMAX;
 constexpr int TSTRIDE = ANISO_LMAX;                         // table row length in LDS
 constexpr int TDIR = 2 * KT * TSTRIDE;                      // one direction: chi then chi'
 constexpr int64_t kMaxGrid = int64_t(1) << 22;
@@ -143,9 +142,12 @@ __device__ void build_meta(int space, int a, int b, double w0, double w1, const 
 template <typename Real>
 __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t item0) {
   __shared__ Real s_tab[3 * TDIR];          // direction d: chi^<r>_k(zeta_l) at d TDIR + r KT TSTRIDE + k TSTRIDE + l
-  __shared__ Real s_F[MF * QMAX];           // fields, point q = qA + LA (qB + LB qC)
-  __shared__ Real s_A[MT * ANISO_LMAX * ANISO_LMAX];
-  __shared__ Real s_B[MH * ANISO_LMAX * ANISO_LMAX * ANISO_LMAX];
+  // fields (point q = qA + LA (qB + LB qC)), then P pairs' stage-A and stage-B buffers,
+  // sized by the host for this launch
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  Real* const s_F = reinterpret_cast<Real*>(s_dyn);
+  Real* const s_A = s_F + A.lds_fields;
+  Real* const s_B = s_A + A.pairs * A.lds_a;
   __shared__ Meta m;
   __shared__ int s_bad;
 
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
   // at a time when the stage buffers hold P pairs' intermediates: small blocks would
   // otherwise leave most threads idle between two barriers.
   const int nAs = m.ng * LC * LB, nBs = m.nh * LC * nB;
-  const int P = max(1, min(min(int(sizeof(s_A) / sizeof(Real)) / nAs, int(sizeof(s_B) / sizeof(Real)) / nBs), 16));
+  const int P = A.pairs;                    // the host sized the buffers for P pairs of any block
   __shared__ int s_pair[ANISO_LMAX * ANISO_LMAX];
   __shared__ int s_npair;
   if (tid == 0) {
@@ -365,15 +367,39 @@ __global__ void __launch_bounds__(NTA) k_aniso(AnisoArgs A, int nblk, int64_t it
 
 }  // namespace
 
-hipError_t launch_aniso(int prec, const AnisoArgs& a, hipStream_t st) {
-  const int nblk = (a.space == SP_H1 || a.space == SP_L2) ? 1 : 6;
+hipError_t launch_aniso(int prec, const AnisoArgs& a0, hipStream_t st) {
+  AnisoArgs a = a0;
+  const int sp = a.space, nblk = (sp == SP_H1 || sp == SP_L2) ? 1 : 6;
+  // upper bounds over the blocks of a space: distinct fields, stage-A and stage-C groups
+  const int nf = sp == SP_H1 ? 7 : sp == SP_HCURL ? 5 : sp == SP_HDIV ? 2 : 1;
+  const int ng = sp == SP_H1 ? MT : sp == SP_HCURL ? 5 : sp == SP_HDIV ? 2 : 1;
+  const int nh = sp == SP_H1 || sp == SP_HCURL ? MH : sp == SP_HDIV ? 2 : 1;
+  const int dB = a.dir[1], dC = a.dir[2];
+  const int rB = sp == SP_L2 ? a.q[dB] : a.q[dB] + 1;      // largest range of direction B over components
+  const int LB = a.L[dB], LC = a.L[dC];
+  a.lds_fields = nf * a.L[0] * a.L[1] * a.L[2];
+  a.lds_a = ng * LC * LB;
+  const int per_b = nh * LC * rB * rB;
+  // as many pairs per barrier interval as fit in about 40 KB (three workgroups per CU
+  // in FP64), at least one, at most 16
+  const int64_t budget = (int64_t(40) << 10) / (prec ? 4 : 8) - a.lds_fields;
+  a.pairs = int(std::max<int64_t>(1, std::min<int64_t>(16, budget / (a.lds_a + per_b))));
+  const size_t lds = size_t(a.lds_fields + a.pairs * (a.lds_a + per_b)) * (prec ? 4 : 8);
   const int64_t items = a.n_elem * nblk;
+  hipError_t err = hipSuccess;
+  if (prec)
+    err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aniso<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  else
+    err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aniso<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (err != hipSuccess) return err;
   for (int64_t i0 = 0; i0 < items; i0 += kMaxGrid) {
     const unsigned grid = unsigned(std::min(kMaxGrid, items - i0));
     if (prec)
-      hipLaunchKernelGGL(k_aniso<float>, dim3(grid), dim3(NTA), 0, st, a, nblk, i0);
+      hipLaunchKernelGGL(k_aniso<float>, dim3(grid), dim3(NTA), lds, st, a, nblk, i0);
     else
-      hipLaunchKernelGGL(k_aniso<double>, dim3(grid), dim3(NTA), 0, st, a, nblk, i0);
+      hipLaunchKernelGGL(k_aniso<double>, dim3(grid), dim3(NTA), lds, st, a, nblk, i0);
   }
   return hipGetLastError();
 }
