@@ -160,11 +160,11 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
 
 /* Non-uniform orders (p1, p2, p3) (text after Algorithm 2): the 1D pair of
  * direction d has order p[d] (device-independent host array int32[3], each in
- * [1, 8]), so component a spans R_d(a) functions in direction d: H1 p_d+1;
+ * [1, 10]), so component a spans R_d(a) functions in direction d: H1 p_d+1;
  * L2 p_d; H(div) p_d+1 if d = a else p_d; H(curl) p_d if d = a else p_d+1,
  * flat index as for uniform orders (i1 fastest, components in order).  Each
  * coordinate takes its own Gauss rule (p_d + 1 points, p_d for L2), or opts->nq
- * points in every direction when nq > 0 (at most 9); the direction of least
+ * points in every direction when nq > 0 (at most 11); the direction of least
  * order is contracted last, in the outermost loop.  Output, geometry, status,
  * weights and precision as for dpg_gram_integrate, with packed length
  * n (n+1)/2, n = dpg_gram_dim_aniso(space, p).  Quadrature path only

@@ -7,7 +7,7 @@
 
 namespace dpg {
 
-constexpr int ANISO_PMAX = 8;                 // largest order per direction
+constexpr int ANISO_PMAX = 10;                // largest order per direction (H1 at 10, 10, 10 in FP64 fills most of the LDS)
 constexpr int ANISO_LMAX = ANISO_PMAX + 1;    // largest point count per direction
 
 struct AnisoArgs {

@@ -385,6 +385,7 @@ hipError_t launch_aniso(int prec, const AnisoArgs& a0, hipStream_t st) {
   const int64_t budget = (int64_t(40) << 10) / (prec ? 4 : 8) - a.lds_fields;
   a.pairs = int(std::max<int64_t>(1, std::min<int64_t>(16, budget / (a.lds_a + per_b))));
   const size_t lds = size_t(a.lds_fields + a.pairs * (a.lds_a + per_b)) * (prec ? 4 : 8);
+  if (lds + sizeof(Meta) + 3 * TDIR * (prec ? 4 : 8) + 1024 > size_t(160) << 10) return hipErrorInvalidValue;
   const int64_t items = a.n_elem * nblk;
   hipError_t err = hipSuccess;
   if (prec)
