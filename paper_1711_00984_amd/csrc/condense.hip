@@ -6,16 +6,18 @@
 // factor overwrites them in place: G = U^T U, U upper triangular with a
 // positive diagonal (LAPACK's packed 'U' convention).
 //
-// One workgroup per element (per element and 16 right-hand sides for the
-// solve).  Both kernels walk 16-row blocks of a triangular solve with U^T:
-// each block first subtracts the product of the rows already finished (a
-// 16 x 16 x K contraction over packed columns, on FP64 or FP32 MFMA, the
-// 4-wide k steps dealt round robin to the four waves and summed through LDS),
-// then 16 lanes finish the block against its 16 x 16 diagonal block of U.
-// The factorization is the same walk with the Gram's own columns as
-// right-hand sides, one 16-column panel at a time (the up-looking order:
-// column j of U solves U[:j, :j]^T u = G[:j, j]), closed by the Cholesky
-// factor of the panel's diagonal block.
+// One workgroup of four waves per element (per element and 16 right-hand sides
+// for the solve).  Both kernels walk 16-row blocks of a triangular solve with
+// U^T: a block first loses the product of the rows already finished (a
+// 16 x 16 x K contraction over packed columns on FP64 or FP32 MFMA), then 16 lanes
+// finish it against the block's 16 x 16 diagonal block of U.  The factorization is
+// that walk with the Gram's own columns as right-hand sides, one 64-column panel at
+// a time (the up-looking order: column j of U solves U[:j, :j]^T u = G[:j, j]),
+// each wave owning a 16-column tile of the panel; inside the panel's diagonal block
+// the wave holding the diagonal tile factors it (unblocked Cholesky in registers)
+// before the waves to its right substitute with it.  The solve splits each block's
+// contraction over the four waves (4-wide k steps dealt round robin, summed through
+// LDS).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
