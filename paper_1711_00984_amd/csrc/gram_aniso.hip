@@ -8,12 +8,12 @@
 // contracted in the order dir[0], dir[1], dir[2] (the least order).  dir[0] is
 // xi3, the slowest index of the flat numbering, whenever xi3 is not the least
 // order, so that a diagonal block can skip the pairs i3 > j3 whole; otherwise
-// the last stage skips them.  The integrands are the terms of
-// Sections 2.3-2.6 (the same integrands as the
-// uniform kernels; component a of a space spans R_d(a) functions in direction
-// d, from p_d).
+// the last stage skips them.  The integrands are the terms of Sections 2.3-2.6,
+// as in the uniform kernels; component a of a space spans R_d(a) functions in
+// direction d, from p_d.
 //
-// One workgroup per (element, component block a <= b), FP64 or FP32 VALU:
+// One workgroup per (element, component block a <= b), FP64 or FP32 VALU, LDS
+// sized by the host for the launch's point counts and ranges:
 //   fields  c_t at all L1 L2 L3 points (FP64 metric, times the weights) -> LDS
 //   for each pair (iA, jA) of the first direction (several at once for small blocks):
 //     stage A: A_g[qC][qB]             = sum_qA c_t T_A T_A            (terms -> groups g)
