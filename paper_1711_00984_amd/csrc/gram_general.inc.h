@@ -542,8 +542,11 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // [y = yt*16 + lr], entry I + J(J+1)/2 of the packed column J.  Buffer stores without
     // branches: a lane with nothing to store gets an offset past the element's range, which
     // the buffer unit discards.  J < 2^13, so J(J+1) is one 24-bit multiply-add.
-    auto st = [&](auto PI, auto YC, const Acc (&acc1)[YB]) {
+    // DG: the pair is a diagonal pair of the full x tiling (its lower triangle dropped); a
+    // wave-uniform property of the pair, so the other pairs' stores skip that mask
+    auto st_body = [&](auto PI, auto YC, auto DG, const Acc (&acc1)[YB]) {
       constexpr int pi = decltype(PI)::value, yc = decltype(YC)::value;
+      constexpr bool dg = decltype(DG)::value;
       const int Ib = Ibp[pi], Jb = Jbp[pi];
       static_for<YB>([&](auto YY) {
         constexpr int yt = yc * YB + decltype(YY)::value;
@@ -558,10 +561,10 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
             const unsigned JJ = __umul24(J, J) + J;
             unsigned off = (JJ << (sizeof(Real) == 8 ? 2 : 1)) + ya8 + xa8[r];
             if constexpr (DIAG) off = (xlt[r] || i1 <= j1) ? off : kDropOff;
-            if constexpr (A == B && !DIAG && diag_inline_ok(S, P)) {
+            if constexpr (dg) {
               const unsigned il = unsigned(i1 * int(sizeof(Real))) + xa8[r];
               const unsigned jl = (unsigned(j1) + xb[r]) * unsigned(sizeof(Real));
-              off = (dgp[pi] && il > jl) ? kDropOff : off;
+              off = il > jl ? kDropOff : off;
             }
             if constexpr (CF::HD && !DIAG) {
               if (hdw[pi]) {
@@ -578,6 +581,17 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
           }
         }
       });
+    };
+    auto st = [&](auto PI, auto YC, const Acc (&acc1)[YB]) {
+      constexpr int pi = decltype(PI)::value;
+      if constexpr (A == B && !DIAG && diag_inline_ok(S, P)) {
+        if (dgp[pi])
+          st_body(PI, YC, std::true_type{}, acc1);
+        else
+          st_body(PI, YC, std::false_type{}, acc1);
+      } else {
+        st_body(PI, YC, std::false_type{}, acc1);
+      }
     };
     // after a diagonal pair: the held column heads of its slab, for this x-tile's 16 columns
     // (j2 = 2 xt, 2 xt + 1), which the same wave held back at the slab's first pair
