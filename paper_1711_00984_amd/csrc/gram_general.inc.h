@@ -544,9 +544,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // the buffer unit discards.  J < 2^13, so J(J+1) is one 24-bit multiply-add.
     // DG: the pair is a diagonal pair of the full x tiling (its lower triangle dropped); a
     // wave-uniform property of the pair, so the other pairs' stores skip that mask
-    auto st_body = [&](auto PI, auto YC, auto DG, const Acc (&acc1)[YB]) {
+    auto st_body = [&](auto PI, auto YC, auto DG, auto HW, const Acc (&acc1)[YB]) {
       constexpr int pi = decltype(PI)::value, yc = decltype(YC)::value;
-      constexpr bool dg = decltype(DG)::value;
+      constexpr bool dg = decltype(DG)::value, hw = decltype(HW)::value;
       const int Ib = Ibp[pi], Jb = Jbp[pi];
       static_for<YB>([&](auto YY) {
         constexpr int yt = yc * YB + decltype(YY)::value;
@@ -566,8 +566,8 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
               const unsigned jl = (unsigned(j1) + xb[r]) * unsigned(sizeof(Real));
               off = il > jl ? kDropOff : off;
             }
-            if constexpr (CF::HD && !DIAG) {
-              if (hdw[pi]) {
+            if constexpr (hw) {
+              {
                 // rows of the column's first line (i3 = 0, so I = i1 + 8 i2) go to LDS
                 const unsigned h = (CF::LN - ((JJ >> 1) & (CF::LN - 1))) & (CF::LN - 1);
                 const unsigned I8 = ya8 + xa8[r];
@@ -582,15 +582,27 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
         }
       });
     };
+    // the pair's mask and head holding are wave-uniform: one branch per pair, not per store
+    auto st_hd = [&](auto PI, auto YC, auto DG, const Acc (&acc1)[YB]) {
+      constexpr int pi = decltype(PI)::value;
+      if constexpr (CF::HD && !DIAG) {
+        if (hdw[pi])
+          st_body(PI, YC, DG, std::true_type{}, acc1);
+        else
+          st_body(PI, YC, DG, std::false_type{}, acc1);
+      } else {
+        st_body(PI, YC, DG, std::false_type{}, acc1);
+      }
+    };
     auto st = [&](auto PI, auto YC, const Acc (&acc1)[YB]) {
       constexpr int pi = decltype(PI)::value;
       if constexpr (A == B && !DIAG && diag_inline_ok(S, P)) {
         if (dgp[pi])
-          st_body(PI, YC, std::true_type{}, acc1);
+          st_hd(PI, YC, std::true_type{}, acc1);
         else
-          st_body(PI, YC, std::false_type{}, acc1);
+          st_hd(PI, YC, std::false_type{}, acc1);
       } else {
-        st_body(PI, YC, std::false_type{}, acc1);
+        st_hd(PI, YC, std::false_type{}, acc1);
       }
     };
     // after a diagonal pair: the held column heads of its slab, for this x-tile's 16 columns
