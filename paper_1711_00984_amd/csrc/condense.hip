@@ -55,14 +55,15 @@ constexpr int NW = NT / 64;
 constexpr int64_t kMaxGrid = int64_t(1) << 22;   // workgroups per launch
 
 // This wave's share of C[i][j] = sum_{k0 <= k < k1} A(i, k) B(k, j), 0 <= i, j < 16:
-// 4-wide k steps go round robin to the NW waves.  a(i, k) and b(k, j) are only
-// called for k0 <= k < k1 and return zero outside the matrices.  Full waves only.
-template <typename Real, typename FA, typename FB>
+// 4-wide k steps go round robin to NWV waves (wv: this wave's place among them).
+// a(i, k) and b(k, j) are only called for k0 <= k < k1 and return zero outside the
+// matrices.  Full waves only.
+template <typename Real, int NWV = NW, typename FA, typename FB>
 __device__ __forceinline__ typename Mfma<Real>::acc wave_gemm(FA a, FB b, int64_t k0, int64_t k1, int wv, int lane) {
   typedef Mfma<Real> M;
   typename M::acc c = {0, 0, 0, 0};
   const int i = lane & 15, kk = lane >> 4;
-  constexpr int64_t step = 4 * NW;
+  constexpr int64_t step = 4 * NWV;
   int64_t kb = k0 + 4 * wv;
   for (; kb + 3 * step < k1; kb += 4 * step) {   // four steps, loads first
     Real av[4], bv[4];
@@ -339,6 +340,105 @@ __global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64
   }
 }
 
+// The solve for small Grams (n <= 256, where the round-robin contraction is short and
+// the workgroups many): each wave owns 16 right-hand sides (64 per workgroup) and
+// contracts its own tile over all k, so U is read once per 64 right-hand sides and
+// there is no cross-wave sum; the 16 x 16 diagonal block of U is fetched once per
+// row block for the four waves.
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_potrs_w(const Real* __restrict__ up, int64_t n, int64_t n_elem, int64_t nrhs,
+                                                int64_t e0, Real* __restrict__ b) {
+  typedef Mfma<Real> M;
+  constexpr int CW = NB * NW;               // right-hand sides per workgroup
+  __shared__ Real s_S[NW][NB][NB + 1];      // each wave's tile, row-major
+  __shared__ Real s_T[NB][2 * NB];          // forward: U[ib + r][ib + c] at [r][c]; backward: at [c][NB - 1 - r]
+  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r] (rows past n: 1)
+  const int64_t nblk = (nrhs + CW - 1) / CW;
+  const int64_t e = e0 + int64_t(blockIdx.x) / nblk, cb = int64_t(blockIdx.x) % nblk;
+  if (e >= n_elem) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
+  const Real* u = up + e * (n * (n + 1) / 2);
+  const int64_t c0 = cb * CW + NB * wv;     // this wave's first right-hand side
+  const int wc = int(std::max<int64_t>(0, std::min<int64_t>(NB, nrhs - c0)));
+  Real* x = b + e * n * nrhs + c0 * n;      // its column j at x + j n (not read when wc = 0)
+  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
+
+  auto fetch_t = [&](int64_t ib, int h) {
+    const int r = tid & 15, c = tid >> 4;
+    return (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
+  };
+  auto put_t = [&](Real t, bool fwd) {
+    const int r = tid & 15, c = tid >> 4;
+    if (fwd)
+      s_T[r][c] = t;
+    else
+      s_T[c][NB - 1 - r] = t;
+    if (r == c) s_rd[r] = Real(1) / t;
+  };
+  // right-hand side entries of this lane's accumulator slots
+  auto fetch_x = [&](int64_t ib, int h, Real (&xv)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = M::row(lg, r);
+      xv[r] = (row < h && li < wc) ? x[li * n + ib + row] : Real(0);
+    }
+  };
+  auto put_s = [&](const Real (&xv)[4], const typename M::acc& c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s_S[wv][M::row(lg, r)][li] = xv[r] - c[r];
+  };
+
+  // U^T y = b, top down.
+  for (int64_t ib = 0; ib < n; ib += NB) {
+    const int h = int(std::min<int64_t>(NB, n - ib));
+    const Real tv = fetch_t(ib, h);
+    Real xv[4];
+    fetch_x(ib, h, xv);
+    typename M::acc c = {0, 0, 0, 0};
+    if (wc > 0) c = wave_gemm_own<Real>(u + colp(ib + li), x + li * n, li < h, li < wc, ib, lane);
+    put_s(xv, c);
+    put_t(tv, true);
+    __syncthreads();
+    if (wc > 0 && lane < NB) {              // U[Ib, Ib]^T y = s, rows top down
+      const int j = lane;
+      Real v[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v[r] = s_S[wv][r][j];
+      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
+                       [&](int k, Real y) {
+                         if (j < wc && k < h) x[j * n + ib + k] = y;
+                       });
+    }
+    __syncthreads();
+  }
+  // U x = y, bottom up.
+  for (int64_t ib = ((n - 1) / NB) * NB; ib >= 0; ib -= NB) {
+    const int h = int(std::min<int64_t>(NB, n - ib));
+    const Real tv = fetch_t(ib, h);
+    Real xv[4];
+    fetch_x(ib, h, xv);
+    typename M::acc c = {0, 0, 0, 0};
+    if (wc > 0)
+      c = wave_gemm<Real, 1>([&](int i, int64_t k) { return i < h ? u[colp(k) + ib + i] : Real(0); },
+                             [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); }, ib + h, n, 0, lane);
+    put_s(xv, c);
+    put_t(tv, false);
+    __syncthreads();
+    if (wc > 0 && lane < NB) {              // U[Ib, Ib] x = s, step k is row NB - 1 - k
+      const int j = lane;
+      Real v[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v[r] = s_S[wv][NB - 1 - r][j];
+      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; },
+                       [&](int k) { return s_rd[NB - 1 - k]; }, [&](int k, Real y) {
+                         const int r = NB - 1 - k;
+                         if (j < wc && r < h) x[j * n + ib + r] = y;
+                       });
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_potrf(int prec, void* ap, int64_t n, int64_t n_elem, int32_t* info, hipStream_t st) {
@@ -357,17 +457,28 @@ hipError_t launch_potrf(int prec, void* ap, int64_t n, int64_t n_elem, int32_t* 
 }
 
 hipError_t launch_potrs(int prec, const void* up, int64_t n, int64_t n_elem, int64_t nrhs, void* b, hipStream_t st) {
-  const int64_t nblk = (nrhs + NB - 1) / NB;
+  const bool wide = n <= 256;               // one tile per wave (64 right-hand sides per workgroup)
+  const int64_t cw = wide ? NB * NW : NB;
+  const int64_t nblk = (nrhs + cw - 1) / cw;
   const int64_t per = std::max<int64_t>(1, kMaxGrid / nblk);     // elements per launch
   for (int64_t e0 = 0; e0 < n_elem; e0 += per) {
     const int64_t ne = std::min(per, n_elem - e0);
     const unsigned grid = unsigned(ne * nblk);
-    if (prec)
-      hipLaunchKernelGGL(k_potrs<float>, dim3(grid), dim3(NT), 0, st, static_cast<const float*>(up), n, e0 + ne,
-                         nrhs, e0, static_cast<float*>(b));
-    else
-      hipLaunchKernelGGL(k_potrs<double>, dim3(grid), dim3(NT), 0, st, static_cast<const double*>(up), n, e0 + ne,
-                         nrhs, e0, static_cast<double*>(b));
+    if (prec) {
+      auto* u = static_cast<const float*>(up);
+      auto* x = static_cast<float*>(b);
+      if (wide)
+        hipLaunchKernelGGL(k_potrs_w<float>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
+      else
+        hipLaunchKernelGGL(k_potrs<float>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
+    } else {
+      auto* u = static_cast<const double*>(up);
+      auto* x = static_cast<double*>(b);
+      if (wide)
+        hipLaunchKernelGGL(k_potrs_w<double>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
+      else
+        hipLaunchKernelGGL(k_potrs<double>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
+    }
   }
   return hipGetLastError();
 }

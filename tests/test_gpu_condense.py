@@ -138,7 +138,7 @@ def test_failure_special_cases(ctx):
     assert list(info) == [condense.cholesky_upper(G)[1] for G in Gs] == [6, 0, 1]
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 1), (17, 16), (33, 21), (64, 40), (130, 7)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 1), (17, 16), (33, 21), (64, 40), (130, 7), (130, 70), (300, 19)])
 def test_solve(ctx, n, nrhs):
     say("solve", n, nrhs)
     rng = np.random.default_rng(440 + n + nrhs)
