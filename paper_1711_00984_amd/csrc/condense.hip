@@ -7,7 +7,7 @@
 // positive diagonal (LAPACK's packed 'U' convention).
 //
 // One workgroup of four waves per element (per element and 16 right-hand sides
-// for the solve).  Both kernels walk 16-row blocks of a triangular solve with
+// for the solve, 64 when n <= 256).  Both kernels walk 16-row blocks of a triangular solve with
 // U^T: a block first loses the product of the rows already finished (a
 // 16 x 16 x K contraction over packed columns on FP64 or FP32 MFMA), then 16 lanes
 // finish it against the block's 16 x 16 diagonal block of U.  The factorization is
@@ -17,7 +17,7 @@
 // the wave holding the diagonal tile factors it (unblocked Cholesky in registers)
 // before the waves to its right substitute with it.  The solve splits each block's
 // contraction over the four waves (4-wide k steps dealt round robin, summed through
-// LDS).
+// LDS), or for small Grams gives each wave its own 16 right-hand sides.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
