@@ -165,7 +165,9 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
  * flat index as for uniform orders (i1 fastest, components in order).  Each
  * coordinate takes its own Gauss rule (p_d + 1 points, p_d for L2), or opts->nq
  * points in every direction when nq > 0 (at most 11); the direction of least
- * order is contracted last, in the outermost loop.  Output, geometry, status,
+ * order is contracted last, in the outermost loop (equal orders with nq = 0 take the
+ * uniform kernels of dpg_gram_integrate's quadrature path, which compute the same
+ * sums).  Output, geometry, status,
  * weights and precision as for dpg_gram_integrate, with packed length
  * n (n+1)/2, n = dpg_gram_dim_aniso(space, p).  Quadrature path only
  * (DPG_PATH_REDUCED is rejected).  Errors: DPG_EINVAL, DPG_ENOTINIT, DPG_EHIP. */

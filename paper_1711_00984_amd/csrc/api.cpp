@@ -294,6 +294,14 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
   if (o.path == DPG_PATH_REDUCED) return fail(DPG_EINVAL, "non-uniform orders use the quadrature path only");
   if (o.nq < 0 || o.nq > dpg::ANISO_LMAX) return fail(DPG_EINVAL, "nq=%d outside [0, %d]", o.nq, dpg::ANISO_LMAX);
   if (geom->n_elem == 0) return DPG_OK;
+  if (p[0] == p[1] && p[1] == p[2] && o.nq == 0 && p[0] <= ctx->p_max) {
+    // equal orders with the default rule: the uniform quadrature kernels compute the same sums
+    dpg_opts u = o;
+    u.path = DPG_PATH_GENERAL;
+    const dpg::Sched g = dpg::tuned_sched(ctx, space, p[0], u.prec, 0, geom->n_elem);
+    return dpg::launch_elements(ctx, space, p[0], geom, out, u, nullptr, geom->n_elem, nullptr, g,
+                                static_cast<hipStream_t>(stream));
+  }
   dpg::AnisoArgs a{};
   a.geom = geom->data;
   a.geom_kind = geom->kind;

@@ -98,9 +98,15 @@ def test_aniso_high_orders(ctx, space, q):
 @pytest.mark.parametrize("space", SPACES)
 @pytest.mark.parametrize("p", [2, 5])
 def test_uniform_orders_match_the_uniform_kernels(ctx, space, p):
+    """Equal orders: the generic kernel (forced by an explicit nq equal to the
+    default rule) against the uniform kernels, which the entry point itself takes
+    for nq = 0 (bit for bit the uniform call)."""
     X = meshgen.perturbed_hexes(4, seed=620 + p)
-    a = run(ctx, space, (p, p, p), X)
-    u = ctx.gram(space, p, torch.from_numpy(X).cuda()).cpu().numpy()
+    L = p if space == "L2" else p + 1
+    a = run(ctx, space, (p, p, p), X, nq=L)
+    d = run(ctx, space, (p, p, p), X)
+    u = ctx.gram(space, p, torch.from_numpy(X).cuda(), path="general").cpu().numpy()
+    assert np.array_equal(d, u)
     for e in range(4):
         fro, mx = rel(elem(a, e, space, (p,) * 3), elem(u, e, space, (p,) * 3))
         assert fro <= TOL64 and mx <= TOL64, f"{space} p={p} e={e}"
