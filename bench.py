@@ -88,19 +88,41 @@ def _oracle_worker(args):
         return time.perf_counter() - t
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(n_per_worker=1):
+    """The oracle on `workers` host processes (one BLAS thread each), each
+    integrating n_per_worker elements of the benchmark workload.  value = the
+    elements over the slowest worker's compute time (all workers run at once);
+    beside it the per-core busy rate and the wall time with the pool's start."""
     import multiprocessing as mp
     workers = max(1, min(16, os.cpu_count() or 1))
     jobs = [(1712, [w * n_per_worker + i for i in range(n_per_worker)]) for w in range(workers)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(workers) as pool:
         busy = pool.map(_oracle_worker, jobs)
+        pool.close()          # let the workers exit by themselves before the block's terminate()
+        pool.join()
     wall = time.perf_counter() - t0
     n = workers * n_per_worker
-    return {"value": n / wall, "unit": "elements/s", "cores": workers, "kind": "oracle",
+    return {"value": round(n / max(busy), 3), "unit": "elements/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "per_core_elements_per_s": round(n_per_worker / (sum(busy) / workers), 4),
+            "wall_elements_per_s": round(n / wall, 3),
             "sample": f"{n} elements of the benchmark workload (H1, p=7, L=8), FP64 brute-force "
-                      f"O(p^9) quadrature, {workers} processes x 1 BLAS thread; "
-                      f"{sum(busy):.1f} core-seconds, {wall:.1f} s wall (pool start included)"}
+                      f"O(p^9) quadrature, {workers} processes x 1 BLAS thread on {cpu_model()}; "
+                      f"{sum(busy):.1f} core-seconds, slowest worker {max(busy):.2f} s, "
+                      f"{wall:.1f} s wall with the pool's start"}
 
 
 def main():
@@ -162,7 +184,8 @@ def main():
     ms_per_step = 1e3 * wall / a.steps
     value = E * a.steps / wall
     kern_ms = float(np.mean(per))
-    flops = dpg.general_flops(space, p) * E
+    flops = dpg.general_flops(space, p) * E              # stage xi2 over every (i2, j2) of each pair
+    flops_trim = dpg.general_flops_trimmed(space, p) * E  # diagonal pairs' stage xi2 over i2 <= j2 only
     out_bytes = m * out.element_size() * E
     alg_bytes = out_bytes + 24 * 8 * E
     peak = PEAK_FP64_TFLOPS if a.prec == "fp64" else PEAK_FP32_TFLOPS
@@ -173,6 +196,8 @@ def main():
             "kernel": f"k_general<H1,p=7,{'double' if a.prec == 'fp64' else 'float'}>",
             "avg_launch_ms": round(kern_ms, 4),
             "algorithmic": {"flops_per_launch": flops, "bytes_per_launch": alg_bytes,
+                            "flops_per_launch_trimmed": flops_trim,
+                            "tflops_trimmed": round(flops_trim / (kern_ms * 1e-3) / 1e12, 3),
                             "hbm_gbs_achieved": round(alg_bytes / (kern_ms * 1e-3) / 1e9, 1),
                             "hbm_frac": round(alg_bytes / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
     log(f"[bench] {value:.4g} elem/s, kernel {kern_ms:.3f} ms, {achieved:.2f} TFLOP/s, "

@@ -102,8 +102,13 @@ typedef struct {
  * REDUCED (the default for affine and extruded geometry; rejected for
  * trilinear) is the O(p^6) path of Section 2.8.1: exact 1D integrals F^{rs}
  * in all directions for affine maps (Algorithm 10), in xi1 with quadrature in
- * (xi2, xi3) for extruded maps (Algorithm 11).  nq: points per
- * direction, 0 = default (p+1; p for L2); only the default is built.
+ * (xi2, xi3) for extruded maps (Algorithm 11).  nq: Gauss-Legendre points
+ * per direction of the quadrature path, 0 = default (p+1; p for L2, exact
+ * for degree 2 nq - 1 on (0,1), text after (2.22)).  dpg_gram_integrate runs
+ * a rule other than the default on the generic kernel of
+ * dpg_gram_integrate_aniso at orders (p, p, p) (nq in [1, 11], p <= 10; AUTO
+ * then takes the quadrature path for every geometry kind, REDUCED is
+ * rejected: it integrates exactly).  The batched call takes the default only.
  * w0, w1: weights of the value and derivative parts.
  * status: optional device int32[n_elem]; written with DPG_OK or DPG_EJACOBIAN
  * per element.  An element with det J <= 0 at any quadrature point (GENERAL)
@@ -362,8 +367,15 @@ int dpg_host_tables(int L, int kmax, double* zeta, double* w, double* chi, doubl
 /* F[(kmax+1)^2] with F[i * (kmax+1) + j] = int_0^1 chi^<r>_i chi^<s>_j  ((2.90)). */
 int dpg_host_ftable(int r, int s, int kmax, double* F);
 /* Algorithmic work of one element on the GENERAL path: flops of the three
- * staged contractions, and output bytes; -1 on invalid arguments. */
+ * staged contractions (2.23)-(2.25) over the upper block triangle of (i3, j3)
+ * pairs: 2 L^3 per term and pair (xi3), 2 L^2 per merged term, l and (i2, j2)
+ * (xi2), 2 L per group of terms and packed output entry (xi1); -1 on invalid
+ * arguments.  dpg_general_flops counts stage xi2 over every (i2, j2) of each
+ * pair (H1 p = 7: 11.43 MFLOP); dpg_general_flops_trimmed counts only i2 <= j2
+ * for the diagonal pairs i3 = j3 of the diagonal blocks, which is all that the
+ * packed upper triangle needs and what the kernels compute (H1 p = 7: 11.17). */
 double dpg_general_flops(int space, int p);
+double dpg_general_flops_trimmed(int space, int p);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* dpg_last_error(void);

@@ -129,6 +129,11 @@ double dpg_general_flops(int space, int p) {
   return dpg::general_flops(space, p);
 }
 
+double dpg_general_flops_trimmed(int space, int p) {
+  if (!dpg::valid_space(space) || p < 1 || p > DPG_P_MAX) return -1.0;
+  return dpg::general_flops(space, p, true);
+}
+
 int dpg_host_tables(int L, int kmax, double* zeta, double* w, double* chi, double* dchi) {
   if (L < 1 || L > 64 || kmax < 0 || kmax > dpg::KT - 1 || !zeta || !w || !chi || !dchi)
     return fail(DPG_EINVAL, "dpg_host_tables: bad arguments");
@@ -205,6 +210,21 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
   if (rc) return rc;
   if (!dpg::valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
   if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
+  if (o.nq != 0 && o.nq != dpg::npoints(space, p)) {
+    // A rule other than the default: the quadrature path with nq points per direction.  The
+    // uniform kernels are built for the default rule only, so the generic kernel of
+    // non-uniform orders integrates it, at orders (p, p, p).
+    if (o.path == DPG_PATH_REDUCED)
+      return fail(DPG_EINVAL, "nq=%d: the reduced path integrates exactly and takes no rule", o.nq);
+    if (o.nq < 1 || o.nq > dpg::ANISO_LMAX)
+      return fail(DPG_EINVAL, "nq=%d outside [1, %d] (default %d)", o.nq, dpg::ANISO_LMAX, dpg::npoints(space, p));
+    if (p > dpg::ANISO_PMAX)
+      return fail(DPG_EINVAL, "nq=%d at p=%d: rules other than the default are supported up to p=%d", o.nq, p,
+                  dpg::ANISO_PMAX);
+    if (geom->n_elem == 0) return DPG_OK;
+    const int32_t q[3] = {p, p, p};
+    return dpg::integrate_aniso(ctx, space, q, geom, out, o, static_cast<hipStream_t>(stream));
+  }
   if (geom->n_elem == 0) return DPG_OK;
   const dpg::Sched g = dpg::tuned_sched(ctx, space, p, o.prec, dpg::path_code(geom, o), geom->n_elem);
   return dpg::launch_elements(ctx, space, p, geom, out, o, nullptr, geom->n_elem, nullptr, g,
@@ -302,6 +322,15 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
     return dpg::launch_elements(ctx, space, p[0], geom, out, u, nullptr, geom->n_elem, nullptr, g,
                                 static_cast<hipStream_t>(stream));
   }
+  return dpg::integrate_aniso(ctx, space, p, geom, out, o, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace dpg {
+
+int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
+                    const dpg_opts& o, hipStream_t st) {
   dpg::AnisoArgs a{};
   a.geom = geom->data;
   a.geom_kind = geom->kind;
@@ -330,8 +359,8 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
   a.w0 = o.w0;
   a.w1 = o.w1;
   a.status = o.status;
-  const hipError_t e = dpg::launch_aniso(o.prec, a, static_cast<hipStream_t>(stream));
+  const hipError_t e = dpg::launch_aniso(o.prec, a, st);
   return e == hipSuccess ? DPG_OK : hip_fail(e, "anisotropic launch");
 }
 
-}  // extern "C"
+}  // namespace dpg

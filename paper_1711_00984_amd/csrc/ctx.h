@@ -77,6 +77,11 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
                     const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
                     Sched sched, hipStream_t st);
 
+// Non-uniform orders p[3] (or equal orders with a rule other than the default) on the
+// generic kernel: one rule per direction (opts nq points in every direction when nq > 0).
+int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
+                    const dpg_opts& o, hipStream_t st);
+
 // Schedule from the tuning table (defaults when not tuned).
 Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int64_t n);
 

@@ -914,7 +914,7 @@ hipError_t launch_general_one(const GeneralArgs& a, hipStream_t st) {
   c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
   if (c.diag_inline < 0 || !diag_inline_ok(S, P)) c.diag_inline = diag_inline_ok(S, P) ? 1 : 0;
   const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
-  const int64_t max_items = int64_t(0x7fffffff) / ngroups;
+  const int64_t max_items = launch_items(ngroups);
   for (int64_t base = 0; base < a.n_items; base += max_items) {
     c.item_base = a.item_base + base;
     c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "launch_limits.h"
+
 namespace dpg {
 
 constexpr int PMAX = 11;           // largest order p

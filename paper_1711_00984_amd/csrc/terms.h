@@ -203,11 +203,14 @@ constexpr long long packed_len(int space, int p) {
   return gram_dim(space, p) * (gram_dim(space, p) + 1) / 2;
 }
 
-// Flops of the staged contraction of one element (upper block triangle only,
-// diagonal pairs restricted to i2 <= j2): stage 3 2 L^3 per term and (i3,j3)
-// pair, stage 2 2 L^2 per q slot and (l, i2, j2), stage 1 2 L per group and
-// output entry.
-constexpr double general_flops(int space, int p) {
+// Flops of the staged contraction of one element over the upper block
+// triangle (the (i3, j3) pairs a < b, or a == b and i3 <= j3): stage 3 2 L^3
+// per term and pair, stage 2 2 L^2 per q slot, l and (i2, j2), stage 1 2 L per
+// group and packed output entry.  Stage 2 runs over every (i2, j2) of a pair;
+// with trim_diag the diagonal pairs (a == b, i3 == j3) count only i2 <= j2,
+// the part of their stage 2 that the upper triangle needs (what the kernels
+// compute).
+constexpr double general_flops(int space, int p, bool trim_diag = false) {
   const int L = npoints(space, p);
   const int nc = ncomp(space);
   double f = 0.0;
@@ -220,11 +223,12 @@ constexpr double general_flops(int space, int p) {
       double pairs_full = 0.0, pairs_diag = 0.0;
       if (a == b) { pairs_diag = R3a; pairs_full = R3a * (R3a - 1) / 2.0; }
       else { pairs_diag = 0; pairs_full = double(R3a) * R3b; }
-      const double n2_full = double(R2a) * R2b, n2_diag = R2a * (R2a + 1) / 2.0;
+      const double n2_full = double(R2a) * R2b;
+      const double n2_diag = trim_diag ? R2a * (R2a + 1) / 2.0 : n2_full;
       const double n1 = double(R1a) * R1b;
       const double n1_tri = R1a * (R1a + 1) / 2.0;  // i2 == j2 rows of a diagonal pair
       const double out_full = n1 * n2_full;
-      const double out_diag = n1 * (n2_diag - R2a) + n1_tri * R2a;
+      const double out_diag = n1 * (R2a * (R2a + 1) / 2.0 - R2a) + n1_tri * R2a;
       const double pairs = pairs_full + pairs_diag;
       f += pairs * 2.0 * L * L * L * P.nt;
       f += (pairs_full * n2_full + pairs_diag * n2_diag) * 2.0 * L * L * P.nq;

@@ -86,6 +86,8 @@ _lib.dpg_gram_packed_len.argtypes = [_i, _i]
 _lib.dpg_gram_packed_len.restype = _i64
 _lib.dpg_general_flops.argtypes = [_i, _i]
 _lib.dpg_general_flops.restype = _d
+_lib.dpg_general_flops_trimmed.argtypes = [_i, _i]
+_lib.dpg_general_flops_trimmed.restype = _d
 _lib.dpg_gram_integrate.argtypes = [_vp, _i, _i, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate.restype = _i
 _lib.dpg_gram_integrate_batched.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
@@ -187,7 +189,13 @@ def gram_dim_aniso(space, p):
 
 
 def general_flops(space, p):
+    """Flops of one element's staged contraction, stage xi2 over every (i2, j2)."""
     return float(_lib.dpg_general_flops(space_id(space), p))
+
+
+def general_flops_trimmed(space, p):
+    """The same with stage xi2 of the diagonal pairs over i2 <= j2 only (what the kernels compute)."""
+    return float(_lib.dpg_general_flops_trimmed(space_id(space), p))
 
 
 def default_points(space, p):

@@ -56,12 +56,36 @@ def test_dimensions(dpg):
     assert dpg.gram_dim(4, 3) == -1
 
 
-def test_general_flops_h1_p7(dpg):
-    # staged contraction of one H1 p=7 element: ~1.1e7 flops (stage 1 dominant)
-    f = dpg.general_flops("H1", 7)
-    assert 1.0e7 < f < 1.3e7
+# Algorithmic MFLOP per element of the staged contraction, p = 4..8 (stage xi2 over every
+# (i2, j2) of each needed (i3, j3) pair), as tabulated for the benchmark configurations.
+CONTRACT_MFLOP = {
+    "H1": [0.52, 1.71, 4.71, 11.43, 25.13],
+    "HCURL": [1.90, 6.79, 19.98, 50.95, 116.38],
+    "HDIV": [0.65, 2.53, 7.88, 20.98, 49.60],
+    "L2": [0.02, 0.10, 0.34, 0.98, 2.43],
+}
+
+
+def test_general_flops_table(dpg):
+    for sp, vals in CONTRACT_MFLOP.items():
+        for p, v in zip(range(4, 9), vals):
+            assert abs(dpg.general_flops(sp, p) / 1e6 - v) <= 0.005 + 1e-9, (sp, p)
+
+
+def test_general_flops_trimmed(dpg):
+    """The trimmed count drops exactly the xi2 stage of the diagonal pairs below the
+    (i2, j2) diagonal: 2 L^2 per merged term, l and (i2 > j2), R3 pairs per diagonal
+    block; H1 has 9 merged terms (q slots), p + 1 functions and L = p + 1 points."""
+    for p in range(1, 12):
+        R = L = p + 1
+        drop = R * (R * (R - 1) // 2) * 2 * L * L * 9
+        assert dpg.general_flops("H1", p) - dpg.general_flops_trimmed("H1", p) == drop
+    for sp in ("HCURL", "HDIV", "L2"):
+        for p in range(1, 12):
+            assert 0 < dpg.general_flops_trimmed(sp, p) <= dpg.general_flops(sp, p)
+    assert dpg.general_flops("H1", 12) == -1 and dpg.general_flops_trimmed(7, 3) == -1
     # grows like p^7: ratio p=8 / p=7 ~ (9/8)^7
-    r = dpg.general_flops("H1", 8) / f
+    r = dpg.general_flops("H1", 8) / dpg.general_flops("H1", 7)
     assert 1.8 < r < 2.6
 
 

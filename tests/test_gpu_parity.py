@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 SPACES = ["H1", "HCURL", "HDIV", "L2"]
 TOL64 = 1e-12
-FP32_REL = 2e-6
+FP32_REL = 5e-7     # twice the largest error measured against the oracle (FP32 error table)
 
 
 def say(*a):
@@ -39,9 +39,9 @@ def ctx(dpg):
     c.close()
 
 
-def run(ctx, space, p, geom_np, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0, status=None):
+def run(ctx, space, p, geom_np, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0, status=None, nq=0):
     g = torch.from_numpy(np.ascontiguousarray(geom_np)).cuda()
-    out = ctx.gram(space, p, g, kind=kind, prec=prec, path=path, w0=w0, w1=w1, status=status)
+    out = ctx.gram(space, p, g, kind=kind, prec=prec, path=path, w0=w0, w1=w1, status=status, nq=nq)
     torch.cuda.synchronize()
     return out
 
@@ -56,6 +56,33 @@ def compare64(G, R, what):
     fro = np.linalg.norm(G - R) / np.linalg.norm(R)
     mx = np.abs(G - R).max() / np.abs(R).max()
     assert fro <= TOL64 and mx <= TOL64, f"{what}: rel fro {fro:.3e}, rel max {mx:.3e}"
+    return fro
+
+
+def sampled_pairs(n, seed, k=3000):
+    """The whole diagonal plus k random upper-triangle entries (I <= J)."""
+    rng = np.random.default_rng(seed)
+    I = rng.integers(0, n, k)
+    J = rng.integers(0, n, k)
+    I, J = np.minimum(I, J), np.maximum(I, J)
+    return np.concatenate([I, np.arange(n)]), np.concatenate([J, np.arange(n)])
+
+
+def compare_sampled(out_np, e, space, p, kind, geom, seed, what, tol=TOL64, L=None):
+    """Entries of element e's packed output against the oracle computed one by one
+    (og.gram_entries), on the diagonal and 3000 random entries: relative error in
+    the Frobenius norm of the sample and (FP64) in its largest entry."""
+    n = shapes.dimension(space, p)
+    m = n * (n + 1) // 2
+    I, J = sampled_pairs(n, seed)
+    ref = og.gram_entries(space, p, kind, geom, I, J, L=L)
+    got = out_np[e * m:(e + 1) * m][og.packed_offset(I, J)].astype(np.float64)
+    fro = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    mx = np.abs(got - ref).max() / np.abs(ref).max()
+    if tol == TOL64:
+        assert fro <= tol and mx <= tol, f"{what}: sampled rel fro {fro:.3e}, rel max {mx:.3e}"
+    else:
+        assert fro <= tol, f"{what}: sampled rel fro {fro:.3e}"
     return fro
 
 
@@ -87,6 +114,23 @@ def test_general_fp64(ctx, space, p):
     out = run(ctx, space, p, X).cpu().numpy()
     for e in range(3):
         compare64(elem(out, e, space, p), og.gram(space, p, "trilinear", X[e]), f"{space} p={p} e={e}")
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [7, 8])
+def test_general_fp64_p7_p8(ctx, space, p):
+    """Orders 7 and 8 on perturbed trilinear hexes, every space: full matrices where
+    n <= 1000 (H1, L2), the diagonal and 3000 entries computed one by one above."""
+    say(f"general fp64 {space} p={p}")
+    X = meshgen.perturbed_hexes(3, seed=700 + 10 * p + SPACES.index(space))
+    out = run(ctx, space, p, X).cpu().numpy()
+    n = shapes.dimension(space, p)
+    for e in (0, 2):
+        if n <= 1000:
+            compare64(elem(out, e, space, p), og.gram(space, p, "trilinear", X[e]), f"{space} p={p} e={e}")
+        else:
+            compare_sampled(out, e, space, p, "trilinear", X[e], seed=e, what=f"{space} p={p} e={e}")
+    assert np.isfinite(out).all()
 
 
 @pytest.mark.parametrize("space", SPACES)
@@ -134,6 +178,58 @@ def test_reduced_fp64(ctx, space, p):
 
 
 @pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("p", [7, 8])
+def test_reduced_fp64_p7_p8(ctx, space, p):
+    """The reduced (constant-Jacobian) path and the quadrature path on the same
+    sheared parallelepipeds at orders 7 and 8: each against sampled oracle
+    entries, and against each other over every entry."""
+    say(f"reduced fp64 {space} p={p}")
+    A = meshgen.affine_parallelepipeds(3, seed=310 + p)
+    red = run(ctx, space, p, A, kind="affine", path="reduced").cpu().numpy()
+    gen = run(ctx, space, p, A, kind="affine", path="general").cpu().numpy()
+    for e in (0, 2):
+        compare_sampled(red, e, space, p, "affine", A[e], seed=10 + e, what=f"reduced {space} p={p} e={e}")
+        compare_sampled(gen, e, space, p, "affine", A[e], seed=10 + e, what=f"general-affine {space} p={p} e={e}")
+    d = np.abs(red - gen).max() / np.abs(red).max()
+    assert d <= TOL64, f"reduced vs general {space} p={p}: {d:.3e}"
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_nq_rule_invariance_affine(ctx, dpg, space):
+    """On affine elements the default rule is exact (text after (2.22)), so raising
+    the point count through dpg_gram_integrate (nq) leaves every Gram unchanged up
+    to rounding; AUTO with nq takes the quadrature path as well."""
+    say(f"nq invariance {space}")
+    for p in (3, 6):
+        A = meshgen.affine_parallelepipeds(3, seed=40 + p)
+        ref = run(ctx, space, p, A, kind="affine", path="general").cpu().numpy()
+        L = dpg.default_points(space, p)
+        for nq in (L + 1, L + 2):
+            for path in ("general", "auto"):
+                out = run(ctx, space, p, A, kind="affine", path=path, nq=nq).cpu().numpy()
+                d = np.abs(out - ref).max() / np.abs(ref).max()
+                say(f"  {space} p={p} nq={nq} {path}: max rel change {d:.2e}")
+                assert d <= TOL64
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_nq_rule_trilinear_vs_oracle(ctx, dpg, space):
+    """On trilinear maps the integrands are rational and G depends on the rule: a
+    requested nq must give the oracle's sum with exactly that rule, below and
+    above the default."""
+    say(f"nq trilinear {space}")
+    p = 3
+    X = meshgen.perturbed_hexes(2, seed=61)
+    L = dpg.default_points(space, p)
+    for nq in (L - 1, L + 2):
+        out = run(ctx, space, p, X, nq=nq).cpu().numpy()
+        for e in range(2):
+            compare64(elem(out, e, space, p), og.gram(space, p, "trilinear", X[e], L=nq), f"{space} nq={nq}")
+        default = run(ctx, space, p, X).cpu().numpy()
+        assert np.abs(out - default).max() > 0          # a different rule, a different sum
+
+
+@pytest.mark.parametrize("space", SPACES)
 @pytest.mark.parametrize("p", [9, 10, 11])
 def test_high_order_sampled(ctx, space, p):
     say(f"high order sampled {space} p={p}")
@@ -178,9 +274,14 @@ def test_empty_and_invalid(ctx, dpg):
     with pytest.raises(dpg.DpgError):
         ctx.gram("H1", 12, X)
     with pytest.raises(dpg.DpgError):
-        ctx.gram("H1", 3, X, nq=7)
+        ctx.gram("H1", 3, X, nq=12)                      # more points than any built rule
+    with pytest.raises(dpg.DpgError):
+        ctx.gram("H1", 11, X, nq=11)                     # other rules up to p = 10 only
     with pytest.raises(dpg.DpgError):
         ctx.gram("H1", 3, X, path="reduced")
+    A = torch.from_numpy(meshgen.affine_parallelepipeds(1, seed=2)).cuda()
+    with pytest.raises(dpg.DpgError):
+        ctx.gram("H1", 3, A, kind="affine", path="reduced", nq=6)   # the reduced path takes no rule
 
 
 def test_config2_full_size_sampled(ctx, dpg):
@@ -345,6 +446,7 @@ def test_every_schedule_agrees(ctx, dpg, tmp_path, space, p):
     X = meshgen.perturbed_hexes(n, seed=81)
     ns = sum(r[2] for r in shapes.ranges(space, p))
     ref = {e: og.gram(space, p, "trilinear", X[e]) for e in (0, n - 1)} if p <= 7 else {}
+    sampled = (0, n - 1) if p > 7 else ()
     for prec in ("fp64", "fp32"):
         outs = []
         for G in sorted({1, 2, 3, ns}):
@@ -361,6 +463,9 @@ def test_every_schedule_agrees(ctx, dpg, tmp_path, space, p):
             else:
                 fro = np.linalg.norm(G_ - R) / np.linalg.norm(R)
                 assert fro <= FP32_REL, f"{space} p={p} fp32 element {e}: {fro:.3e}"
+        for e in sampled:
+            compare_sampled(outs[0], e, space, p, "trilinear", X[e], seed=20 + e, what=f"{space} p={p} {prec} e={e}",
+                            tol=TOL64 if prec == "fp64" else FP32_REL)
 
 
 def test_tune_table_rows(ctx, dpg, tmp_path):
