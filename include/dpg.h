@@ -163,6 +163,24 @@ int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const in
                                const dpg_geometry* geom, const int64_t* out_offset, void* out,
                                const dpg_opts* opts, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dpg_gram_integrate_batched
+ * with the same arguments and the same results bit for bit, allocating no
+ * memory (no hipMalloc or hipFree, no allocating library call), reading nothing
+ * back to the host and never synchronising.  The per-(space, p) element lists
+ * are built on the device, in a fixed array of the library on each device
+ * (4 MiB, held until the process ends), and one launch per (space, p <= ctx
+ * p_max) strides over its list.  At most dpg_noalloc_max_elements() (2^20)
+ * elements per call (DPG_EINVAL above).  Every call on a device shares that
+ * array: calls that overlap on one device (other streams or threads) race and
+ * must be serialised by the caller.  An element whose space or order is invalid
+ * is skipped (output untouched, status word DPG_EINVAL when status is given);
+ * the call itself returns DPG_OK.  nq must be 0.  Asynchronous on stream. */
+int dpg_gram_integrate_batched_noalloc(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                                       const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                                       const dpg_opts* opts, void* stream);
+int64_t dpg_noalloc_max_elements(void);
+
 /* Non-uniform orders (p1, p2, p3) (text after Algorithm 2): the 1D pair of
  * direction d has order p[d] (device-independent host array int32[3], each in
  * [1, 10]), so component a spans R_d(a) functions in direction d: H1 p_d+1;

@@ -29,6 +29,15 @@ int size_class(int64_t n) {
 }
 
 static hipError_t launch_general(int space, int p, int prec, const GeneralArgs& a, hipStream_t st) {
+  if (a.list) {
+    switch (space) {
+      case DPG_H1: return launch_general_list_h1(p, prec, a, st);
+      case DPG_HCURL: return launch_general_list_hcurl(p, prec, a, st);
+      case DPG_HDIV: return launch_general_list_hdiv(p, prec, a, st);
+      case DPG_L2: return launch_general_list_l2(p, prec, a, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (space) {
     case DPG_H1: return launch_general_h1(p, prec, a, st);
     case DPG_HCURL: return launch_general_hcurl(p, prec, a, st);
@@ -60,7 +69,7 @@ int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const 
 
 int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
-                    Sched sched, hipStream_t st) {
+                    Sched sched, hipStream_t st, const int32_t* list) {
   const int L = npoints(space, p);
   if (o.nq != 0 && o.nq != L)
     return fail(DPG_EINVAL, "nq=%d: only the default point count (%d) is built", o.nq, L);
@@ -81,6 +90,7 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
   a.out_offset = out_offset;
   a.slab_group = sched.slab_group;
   a.diag_inline = sched.diag;
+  a.list = list;
   const int pc = path_code(geom, o);
   const hipError_t e = pc == 2 ? launch_extruded(space, p, o.prec, a, st)
                      : pc == 1 ? launch_affine(space, p, o.prec, a, st)
@@ -162,6 +172,8 @@ int dpg_tables_build(int p_max, void* stream, dpg_ctx** out) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(DPG_ENODEV, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  const int na = dpg::noalloc_init(dev);
+  if (na != DPG_OK) return na;
 
   std::vector<double> t64(dpg::TABLE_LEN), f64(dpg::FTAB_LEN);
   std::vector<float> t32(dpg::TABLE_LEN), f32(dpg::FTAB_LEN);

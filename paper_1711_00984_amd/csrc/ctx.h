@@ -73,9 +73,12 @@ int check_common(const dpg_ctx* ctx, const dpg_geometry* geom, void* out, const 
 
 // Launch the kernels of one (space, p) over n_items elements (elem_ids maps
 // items to elements, nullptr = identity; out_offset nullptr = e * packed_len).
+// With list, a listed launch: the item count and the first entry of elem_ids are
+// read from the device ({count, first} at list), and n_items is only the expected
+// count, which sizes the grid and the slab groups.
 int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, const int32_t* elem_ids, int64_t n_items, const int64_t* out_offset,
-                    Sched sched, hipStream_t st);
+                    Sched sched, hipStream_t st, const int32_t* list = nullptr);
 
 // Non-uniform orders p[3] (or equal orders with a rule other than the default) on the
 // generic kernel: one rule per direction (opts nq points in every direction when nq > 0).
@@ -86,5 +89,9 @@ int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_g
 Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int64_t n);
 
 void destroy_plans(dpg_ctx* ctx);
+
+// Take the device address of the allocation-free batch's list array on device dev
+// (the current device); once per device, from dpg_tables_build.
+int noalloc_init(int dev);
 
 }  // namespace dpg

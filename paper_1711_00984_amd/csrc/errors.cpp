@@ -3,24 +3,21 @@
 
 #include <cstdarg>
 #include <cstdio>
-#include <string>
 
 namespace dpg {
 
 namespace {
-thread_local std::string g_err;
+thread_local char g_err[512];   // fixed storage: recording an error allocates nothing
 }
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  std::vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
-const char* last_error() { return g_err.c_str(); }
+const char* last_error() { return g_err; }
 
 }  // namespace dpg

@@ -99,119 +99,133 @@ __device__ __forceinline__ void column(const Real* sF, const Real (*sC)[3][10], 
   }
 }
 
-template <int S, int P, typename Real>
+template <int S, int P, typename Real, bool LISTED>
 __global__ void __launch_bounds__(NT_AFF) k_affine(GeneralArgs ga) {
   using Sh = AShape<S, P>;
   __shared__ Real s_F[FTAB_LEN];
   __shared__ Real s_C[3][3][10];   // term coefficients of block (a, b)
   __shared__ int s_bad;
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
   const int G = ga.slab_group;
   const int ngroups = (Sh::NSLAB + G - 1) / G;
-  const int grp = ngroups - 1 - int(blk / ga.n_items);
-  const int64_t item = ga.item_base + blk % ga.n_items;
-  const int64_t e = ga.elem_ids ? int64_t(ga.elem_ids[item]) : item;
-  const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
+  // one (item, slab group) of the launch
+  auto run = [&](int64_t blk, int64_t n_items, const int32_t* ids) {
+    const int grp = ngroups - 1 - int(blk / n_items);
+    const int64_t item = ga.item_base + blk % n_items;
+    const int64_t e = ids ? int64_t(ids[item]) : item;
+    const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
 
-  const Real* fR = static_cast<const Real*>(ga.ftabR);
-  for (int i = tid; i < FTAB_LEN; i += NT_AFF) s_F[i] = fR[i];
-  if (tid < 32) {
-    // every one of these threads evaluates the constant metric; thread 3 a + b
-    // writes the coefficients of block (a, b)
-    const double* g = ga.geom + e * 12;
-    double J[3][3], adj[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) J[i][j] = g[3 + 3 * i + j];
-    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-    const double idet = 1.0 / det;
-    if (tid == 0) s_bad = !(det > 0.0);
-    auto fv = [&](int f) -> double {
-      if (f == FLD_DETJ) return det;
-      if (f == FLD_IDETJ) return idet;
-      if (fld_is_D(f)) {
-        const int s = f - FLD_D11, a = sym_a(s), bb = sym_b(s);
-        return (adj[a][0] * adj[bb][0] + adj[a][1] * adj[bb][1] + adj[a][2] * adj[bb][2]) * idet;
-      }
-      const int s = f - FLD_C11, a = sym_a(s), bb = sym_b(s);
-      return (J[0][a] * J[0][bb] + J[1][a] * J[1][bb] + J[2][a] * J[2][bb]) * idet;
-    };
-    sfor<Sh::NC>([&](auto AA) {
-      constexpr int a = decltype(AA)::value;
-      sfor<Sh::NC>([&](auto BB) {
-        constexpr int bb = decltype(BB)::value;
-        if constexpr (a <= bb) {
-          if (tid == 3 * a + bb) {
-            constexpr Plan PL = APlan<S, a, bb>::PL;
-            sfor<10>([&](auto T) {
-              constexpr int t = decltype(T)::value;
-              double c = 0.0;
-              if constexpr (t < PL.nt)
-                c = PL.t[t].sign * fv(PL.t[t].field) * (field_weight(S, PL.t[t].field) ? ga.w1 : ga.w0);
-              s_C[a][bb][t] = static_cast<Real>(c);
-            });
+    const Real* fR = static_cast<const Real*>(ga.ftabR);
+    for (int i = tid; i < FTAB_LEN; i += NT_AFF) s_F[i] = fR[i];
+    if (tid < 32) {
+      // every one of these threads evaluates the constant metric; thread 3 a + b
+      // writes the coefficients of block (a, b)
+      const double* g = ga.geom + e * 12;
+      double J[3][3], adj[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i][j] = g[3 + 3 * i + j];
+      adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+      const double idet = 1.0 / det;
+      if (tid == 0) s_bad = !(det > 0.0);
+      auto fv = [&](int f) -> double {
+        if (f == FLD_DETJ) return det;
+        if (f == FLD_IDETJ) return idet;
+        if (fld_is_D(f)) {
+          const int s = f - FLD_D11, a = sym_a(s), bb = sym_b(s);
+          return (adj[a][0] * adj[bb][0] + adj[a][1] * adj[bb][1] + adj[a][2] * adj[bb][2]) * idet;
+        }
+        const int s = f - FLD_C11, a = sym_a(s), bb = sym_b(s);
+        return (J[0][a] * J[0][bb] + J[1][a] * J[1][bb] + J[2][a] * J[2][bb]) * idet;
+      };
+      sfor<Sh::NC>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        sfor<Sh::NC>([&](auto BB) {
+          constexpr int bb = decltype(BB)::value;
+          if constexpr (a <= bb) {
+            if (tid == 3 * a + bb) {
+              constexpr Plan PL = APlan<S, a, bb>::PL;
+              sfor<10>([&](auto T) {
+                constexpr int t = decltype(T)::value;
+                double c = 0.0;
+                if constexpr (t < PL.nt)
+                  c = PL.t[t].sign * fv(PL.t[t].field) * (field_weight(S, PL.t[t].field) ? ga.w1 : ga.w0);
+                s_C[a][bb][t] = static_cast<Real>(c);
+              });
+            }
           }
+        });
+      });
+    }
+    __syncthreads();
+    Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
+    const bool bad = s_bad != 0;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    // Columns of the slab group form one contiguous packed range [J0, J1).
+    // Each wave takes a contiguous run of columns holding about a quarter of the
+    // range's entries, so neighbouring columns are written back to back by the
+    // same wave.
+    auto colstart = [&](int slab) {   // first column J of a slab (or the end)
+      int o = 0;
+      int J = 0;
+      sfor<Sh::NC>([&](auto CC) {
+        constexpr int c = decltype(CC)::value;
+        constexpr int n = Sh::R(c, 2), w = Sh::R(c, 0) * Sh::R(c, 1);
+        if (slab >= o && slab < o + n) J = Sh::OFF(c) + (slab - o) * w;
+        o += n;
+      });
+      return slab >= Sh::NSLAB ? int(Sh::OFF(Sh::NC)) : J;
+    };
+    const int J0 = colstart(s_lo), J1 = colstart(s_hi);
+    const double E0 = 0.5 * double(J0) * (J0 + 1), E1 = 0.5 * double(J1) * (J1 + 1);
+    // first column whose entries start at or after packed offset e: J (J+1)/2 >= e
+    auto col_at = [&](double e) {
+      int J = int(floor((sqrt(8.0 * e + 1.0) - 1.0) * 0.5));
+      while (0.5 * double(J) * (J + 1) < e) ++J;
+      while (J > 0 && 0.5 * double(J - 1) * J >= e) --J;
+      return J < J0 ? J0 : (J > J1 ? J1 : J);
+    };
+    const int Jw0 = wave == 0 ? J0 : col_at(E0 + (E1 - E0) * wave / 4.0);
+    const int Jw1 = wave == 3 ? J1 : col_at(E0 + (E1 - E0) * (wave + 1) / 4.0);
+    for (int J = Jw0; J < Jw1; ++J) {
+      Real* col = outp + int64_t(J) * (J + 1) / 2;
+      if (bad) {
+        for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+        continue;
+      }
+      sfor<Sh::NC>([&](auto BB) {
+        constexpr int b = decltype(BB)::value;
+        constexpr int R1b = Sh::R(b, 0), R2b = Sh::R(b, 1);
+        if (J >= Sh::OFF(b) && J < Sh::OFF(b + 1)) {
+          const int c = J - Sh::OFF(b);
+          const int j3 = c / (R1b * R2b), r = c % (R1b * R2b);
+          column<S, P, Real, b>(s_F, s_C, J, r % R1b, r / R1b, j3, col, lane);
         }
       });
-    });
-  }
-  __syncthreads();
-  Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
-  const bool bad = s_bad != 0;
-  const int lane = tid & 63, wave = tid >> 6;
-
-  // Columns of the slab group form one contiguous packed range [J0, J1).
-  // Each wave takes a contiguous run of columns holding about a quarter of the
-  // range's entries, so neighbouring columns are written back to back by the
-  // same wave.
-  auto colstart = [&](int slab) {   // first column J of a slab (or the end)
-    int o = 0;
-    int J = 0;
-    sfor<Sh::NC>([&](auto CC) {
-      constexpr int c = decltype(CC)::value;
-      constexpr int n = Sh::R(c, 2), w = Sh::R(c, 0) * Sh::R(c, 1);
-      if (slab >= o && slab < o + n) J = Sh::OFF(c) + (slab - o) * w;
-      o += n;
-    });
-    return slab >= Sh::NSLAB ? int(Sh::OFF(Sh::NC)) : J;
-  };
-  const int J0 = colstart(s_lo), J1 = colstart(s_hi);
-  const double E0 = 0.5 * double(J0) * (J0 + 1), E1 = 0.5 * double(J1) * (J1 + 1);
-  // first column whose entries start at or after packed offset e: J (J+1)/2 >= e
-  auto col_at = [&](double e) {
-    int J = int(floor((sqrt(8.0 * e + 1.0) - 1.0) * 0.5));
-    while (0.5 * double(J) * (J + 1) < e) ++J;
-    while (J > 0 && 0.5 * double(J - 1) * J >= e) --J;
-    return J < J0 ? J0 : (J > J1 ? J1 : J);
-  };
-  const int Jw0 = wave == 0 ? J0 : col_at(E0 + (E1 - E0) * wave / 4.0);
-  const int Jw1 = wave == 3 ? J1 : col_at(E0 + (E1 - E0) * (wave + 1) / 4.0);
-  for (int J = Jw0; J < Jw1; ++J) {
-    Real* col = outp + int64_t(J) * (J + 1) / 2;
-    if (bad) {
-      for (int I = lane; I <= J; I += 64) col[I] = Real(0);
-      continue;
     }
-    sfor<Sh::NC>([&](auto BB) {
-      constexpr int b = decltype(BB)::value;
-      constexpr int R1b = Sh::R(b, 0), R2b = Sh::R(b, 1);
-      if (J >= Sh::OFF(b) && J < Sh::OFF(b + 1)) {
-        const int c = J - Sh::OFF(b);
-        const int j3 = c / (R1b * R2b), r = c % (R1b * R2b);
-        column<S, P, Real, b>(s_F, s_C, J, r % R1b, r / R1b, j3, col, lane);
-      }
-    });
+    if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
+  };
+  if constexpr (LISTED) {
+    // a listed launch: the item count and the first list entry come from the device,
+    // and the workgroups stride over the (item, slab group) pairs
+    const int64_t n_items = ga.list[0];
+    const int32_t* ids = ga.elem_ids + ga.list[1];
+    for (int64_t blk = blockIdx.x; blk < n_items * ngroups; blk += gridDim.x) {
+      run(blk, n_items, ids);
+      __syncthreads();   // the next item rewrites the shared buffers
+    }
+  } else {
+    run(blockIdx.x, ga.n_items, ga.elem_ids);   // one workgroup per (item, slab group)
   }
-  if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
 }
 
 template <int S, int P, typename Real>
@@ -220,11 +234,15 @@ hipError_t launch_affine_one(const GeneralArgs& a, hipStream_t st) {
   GeneralArgs c = a;
   c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
   const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
+  if (a.list) {
+    hipLaunchKernelGGL((k_affine<S, P, Real, true>), dim3(list_grid(a.n_items, ngroups)), dim3(NT_AFF), 0, st, c);
+    return hipGetLastError();
+  }
   const int64_t max_items = launch_items(ngroups);
   for (int64_t base = 0; base < a.n_items; base += max_items) {
     c.item_base = a.item_base + base;
     c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
-    hipLaunchKernelGGL((k_affine<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_AFF), 0, st, c);
+    hipLaunchKernelGGL((k_affine<S, P, Real, false>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_AFF), 0, st, c);
   }
   return hipGetLastError();
 }

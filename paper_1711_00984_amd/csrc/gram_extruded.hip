@@ -194,7 +194,7 @@ __device__ __forceinline__ void stream_cols(const Real* sF, const Real* sK, int 
   }
 }
 
-template <int S, int P, typename Real>
+template <int S, int P, typename Real, bool LISTED>
 __global__ void __launch_bounds__(NT_EXT) k_extruded(GeneralArgs ga) {
   using Sh = XShape<S, P>;
   constexpr int L = Sh::L;
@@ -207,57 +207,71 @@ __global__ void __launch_bounds__(NT_EXT) k_extruded(GeneralArgs ga) {
   __shared__ int s_bad;
 
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
   const int G = ga.slab_group;
   const int ngroups = (Sh::NSLAB + G - 1) / G;
-  const int grp = ngroups - 1 - int(blk / ga.n_items);
-  const int64_t item = ga.item_base + blk % ga.n_items;
-  const int64_t e = ga.elem_ids ? int64_t(ga.elem_ids[item]) : item;
-  const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
+  // one (item, slab group) of the launch
+  auto run = [&](int64_t blk, int64_t n_items, const int32_t* ids) {
+    const int grp = ngroups - 1 - int(blk / n_items);
+    const int64_t item = ga.item_base + blk % n_items;
+    const int64_t e = ids ? int64_t(ids[item]) : item;
+    const int s_lo = grp * G, s_hi = (s_lo + G < Sh::NSLAB) ? s_lo + G : Sh::NSLAB;
 
-  const Real* fR = static_cast<const Real*>(ga.ftabR);
-  for (int i = tid; i < FTAB_LEN; i += NT_EXT) s_F[i] = fR[i];
-  for (int i = tid; i < 2 * KT * L; i += NT_EXT) s_T[i] = ga.tab64[2 * L + i];
-  if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
-  if (tid < 10) s_X[tid] = ga.geom[e * 10 + tid];
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
+    const Real* fR = static_cast<const Real*>(ga.ftabR);
+    for (int i = tid; i < FTAB_LEN; i += NT_EXT) s_F[i] = fR[i];
+    for (int i = tid; i < 2 * KT * L; i += NT_EXT) s_T[i] = ga.tab64[2 * L + i];
+    if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
+    if (tid < 10) s_X[tid] = ga.geom[e * 10 + tid];
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
 
-  const XSmem sm{s_T, s_z, s_w, s_X, s_fld, s_A, &s_bad};
-  Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
-  bool bad = false;
-  for (int s = s_lo; s < s_hi && !bad; ++s) {
-    sfor<Sh::NC>([&](auto BB) {
-      constexpr int b = decltype(BB)::value;
-      if (bad || s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) return;
-      const int j3 = s - Sh::slab0(b);
-      sfor<b + 1>([&](auto AA) {
-        constexpr int a = decltype(AA)::value;
-        constexpr int ko = Sh::KOFF(a, b);
-        build_k<S, P, Real, a, b>(ga, sm, j3, s_K + ko);
+    const XSmem sm{s_T, s_z, s_w, s_X, s_fld, s_A, &s_bad};
+    Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
+    bool bad = false;
+    for (int s = s_lo; s < s_hi && !bad; ++s) {
+      sfor<Sh::NC>([&](auto BB) {
+        constexpr int b = decltype(BB)::value;
+        if (bad || s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) return;
+        const int j3 = s - Sh::slab0(b);
+        sfor<b + 1>([&](auto AA) {
+          constexpr int a = decltype(AA)::value;
+          constexpr int ko = Sh::KOFF(a, b);
+          build_k<S, P, Real, a, b>(ga, sm, j3, s_K + ko);
+        });
+        bad = s_bad != 0;   // uniform: read after the barrier that closes the last build_k
+        if (!bad) stream_cols<S, P, Real, b>(s_F, s_K, j3, outp);
+        __syncthreads();    // s_K and the field buffers are rebuilt for the next slab
       });
-      bad = s_bad != 0;   // uniform: read after the barrier that closes the last build_k
-      if (!bad) stream_cols<S, P, Real, b>(s_F, s_K, j3, outp);
-      __syncthreads();    // s_K and the field buffers are rebuilt for the next slab
-    });
-  }
-  if (bad) {
-    // |J| <= 0 somewhere: the element's output is zero (every slab group clears its columns)
-    const int lane = tid & 63, wave = tid >> 6;
-    sfor<Sh::NC>([&](auto BB) {
-      constexpr int b = decltype(BB)::value;
-      constexpr int w = Sh::R(b, 0) * Sh::R(b, 1);
-      for (int s = s_lo; s < s_hi; ++s) {
-        if (s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) continue;
-        const int J0 = Sh::OFF(b) + (s - Sh::slab0(b)) * w;
-        for (int J = J0 + wave; J < J0 + w; J += 4) {
-          Real* col = outp + int64_t(J) * (J + 1) / 2;
-          for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+    }
+    if (bad) {
+      // |J| <= 0 somewhere: the element's output is zero (every slab group clears its columns)
+      const int lane = tid & 63, wave = tid >> 6;
+      sfor<Sh::NC>([&](auto BB) {
+        constexpr int b = decltype(BB)::value;
+        constexpr int w = Sh::R(b, 0) * Sh::R(b, 1);
+        for (int s = s_lo; s < s_hi; ++s) {
+          if (s < Sh::slab0(b) || s >= Sh::slab0(b) + Sh::R(b, 2)) continue;
+          const int J0 = Sh::OFF(b) + (s - Sh::slab0(b)) * w;
+          for (int J = J0 + wave; J < J0 + w; J += 4) {
+            Real* col = outp + int64_t(J) * (J + 1) / 2;
+            for (int I = lane; I <= J; I += 64) col[I] = Real(0);
+          }
         }
-      }
-    });
+      });
+    }
+    if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
+  };
+  if constexpr (LISTED) {
+    // a listed launch: the item count and the first list entry come from the device,
+    // and the workgroups stride over the (item, slab group) pairs
+    const int64_t n_items = ga.list[0];
+    const int32_t* ids = ga.elem_ids + ga.list[1];
+    for (int64_t blk = blockIdx.x; blk < n_items * ngroups; blk += gridDim.x) {
+      run(blk, n_items, ids);
+      __syncthreads();   // the next item rewrites the shared buffers
+    }
+  } else {
+    run(blockIdx.x, ga.n_items, ga.elem_ids);   // one workgroup per (item, slab group)
   }
-  if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
 }
 
 template <int S, int P, typename Real>
@@ -266,11 +280,15 @@ hipError_t launch_extruded_one(const GeneralArgs& a, hipStream_t st) {
   GeneralArgs c = a;
   c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
   const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
+  if (a.list) {
+    hipLaunchKernelGGL((k_extruded<S, P, Real, true>), dim3(list_grid(a.n_items, ngroups)), dim3(NT_EXT), 0, st, c);
+    return hipGetLastError();
+  }
   const int64_t max_items = launch_items(ngroups);
   for (int64_t base = 0; base < a.n_items; base += max_items) {
     c.item_base = a.item_base + base;
     c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
-    hipLaunchKernelGGL((k_extruded<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_EXT), 0, st, c);
+    hipLaunchKernelGGL((k_extruded<S, P, Real, false>), dim3(unsigned(c.n_items * ngroups)), dim3(NT_EXT), 0, st, c);
   }
   return hipGetLastError();
 }

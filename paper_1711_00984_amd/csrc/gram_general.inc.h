@@ -824,7 +824,7 @@ template <int S, int P, typename Real> constexpr int min_waves() {
   return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && npoints(S, P) <= DPG_MINW2_LMAX) ? 2 : 1;
 }
 
-template <int S, int P, typename Real>
+template <int S, int P, typename Real, bool LISTED>
 __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general(GeneralArgs ga) {
   using Sh = Shape<S, P>;
   using CF = Cfg<S, P, Real>;
@@ -839,111 +839,134 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
   __shared__ int s_bad;
 
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
   const int G = ga.slab_group;                                // slabs per workgroup
   const int ngroups = (Sh::NSLAB + G - 1) / G;
-  const int grp = ngroups - 1 - int(blk / ga.n_items);        // heaviest slab groups first
-  const int64_t item = ga.item_base + blk % ga.n_items;
-  const int64_t e = ga.elem_ids ? int64_t(ga.elem_ids[item]) : item;
-  const int s_lo = grp * G, s_hi = imin(Sh::NSLAB, s_lo + G);
+  // one (item, slab group) of the launch
+  auto run = [&](int64_t blk, int64_t n_items, const int32_t* ids) {
+    const int grp = ngroups - 1 - int(blk / n_items);                 // heaviest slab groups first
+    const int64_t item = ga.item_base + blk % n_items;
+    const int64_t e = ids ? int64_t(ids[item]) : item;
+    const int s_lo = grp * G, s_hi = imin(Sh::NSLAB, s_lo + G);
 
-  const Real* tR = static_cast<const Real*>(ga.tabR);
-  for (int i = tid; i < CF::T_LEN; i += NTHREADS) s_T[i] = i < 2 * KT * L ? tR[2 * L + i] : Real(0);
-  // stage-3 output buffers: the padding rows (m >= L) and columns (l >= L) stay zero
-  for (int i = tid; i < CF::ABUF * CF::NB * CF::AONE; i += NTHREADS) s_A[i] = Real(0);
-  if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
-  const int ng = geom_stride(ga.geom_kind);
-  if (tid < ng) s_X[tid] = ga.geom[e * ng + tid];
-  if (tid < 80) {
-    // triangular enumeration s = j2 (j2 + 1) / 2 + i2, i2 <= j2
-    int j2 = 0;
-    while ((j2 + 1) * (j2 + 2) / 2 <= tid) ++j2;
-    s_xd[2 * tid] = static_cast<unsigned char>(tid - j2 * (j2 + 1) / 2);
-    s_xd[2 * tid + 1] = static_cast<unsigned char>(j2);
-  }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
+    const Real* tR = static_cast<const Real*>(ga.tabR);
+    for (int i = tid; i < CF::T_LEN; i += NTHREADS) s_T[i] = i < 2 * KT * L ? tR[2 * L + i] : Real(0);
+    // stage-3 output buffers: the padding rows (m >= L) and columns (l >= L) stay zero
+    for (int i = tid; i < CF::ABUF * CF::NB * CF::AONE; i += NTHREADS) s_A[i] = Real(0);
+    if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
+    const int ng = geom_stride(ga.geom_kind);
+    if (tid < ng) s_X[tid] = ga.geom[e * ng + tid];
+    if (tid < 80) {
+      // triangular enumeration s = j2 (j2 + 1) / 2 + i2, i2 <= j2
+      int j2 = 0;
+      while ((j2 + 1) * (j2 + 2) / 2 <= tid) ++j2;
+      s_xd[2 * tid] = static_cast<unsigned char>(tid - j2 * (j2 + 1) / 2);
+      s_xd[2 * tid + 1] = static_cast<unsigned char>(j2);
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
 
-  SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_hd, s_z, s_w, s_X, s_xd, &s_bad};
-  Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
-  // component b owns slabs [slab0(b), slab0(b) + R3(b)); visit the blocks (a, b), a <= b,
-  // for the j3 range of every component the slab group touches
-  bool bad = false;
-  auto jr = [&](int b, int& lo, int& hi) {
-    lo = imax(s_lo, Sh::slab0(b)) - Sh::slab0(b);
-    hi = imin(s_hi, Sh::slab0(b) + Sh::R(b, 2)) - Sh::slab0(b);
-    return lo < hi;
-  };
-  int lo, hi;
-  if (jr(0, lo, hi)) bad = run_block<S, P, Real, 0, 0>(ga, sm, lo, hi, outp);
-  if constexpr (Sh::NC == 3) {
-    if (!bad && jr(1, lo, hi)) {
-      bad = run_block<S, P, Real, 0, 1>(ga, sm, lo, hi, outp);
-      if (!bad) bad = run_block<S, P, Real, 1, 1>(ga, sm, lo, hi, outp);
-    }
-    if (!bad && jr(2, lo, hi)) {
-      bad = run_block<S, P, Real, 0, 2>(ga, sm, lo, hi, outp);
-      if (!bad) bad = run_block<S, P, Real, 1, 2>(ga, sm, lo, hi, outp);
-      if (!bad) bad = run_block<S, P, Real, 2, 2>(ga, sm, lo, hi, outp);
-    }
-  }
-  if (bad) {
-    // element with det J <= 0: its whole output is zero (every slab group does its part)
-    auto colstart = [&](int slab) {   // first column J of a slab
-      int b = 0, j3 = slab;
-#pragma unroll
-      for (int c = 0; c < Sh::NC - 1; ++c)
-        if (b == c && j3 >= Sh::R(c, 2)) { j3 -= Sh::R(c, 2); b = c + 1; }
-      int r12 = Sh::R(0, 0) * Sh::R(0, 1), offb = 0;
-#pragma unroll
-      for (int c = 1; c < Sh::NC; ++c)
-        if (b == c) { r12 = Sh::R(c, 0) * Sh::R(c, 1); offb = Sh::OFF(c); }
-      return int64_t(offb) + int64_t(r12) * j3;
+    SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_hd, s_z, s_w, s_X, s_xd, &s_bad};
+    Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
+    // component b owns slabs [slab0(b), slab0(b) + R3(b)); visit the blocks (a, b), a <= b,
+    // for the j3 range of every component the slab group touches
+    bool bad = false;
+    auto jr = [&](int b, int& lo, int& hi) {
+      lo = imax(s_lo, Sh::slab0(b)) - Sh::slab0(b);
+      hi = imin(s_hi, Sh::slab0(b) + Sh::R(b, 2)) - Sh::slab0(b);
+      return lo < hi;
     };
-    const int64_t J0 = colstart(s_lo);
-    const int64_t J1 = s_hi == Sh::NSLAB ? int64_t(Sh::OFF(Sh::NC)) : colstart(s_hi);
-    for (int64_t i = J0 * (J0 + 1) / 2 + tid; i < J1 * (J1 + 1) / 2; i += NTHREADS) outp[i] = Real(0);
+    int lo, hi;
+    if (jr(0, lo, hi)) bad = run_block<S, P, Real, 0, 0>(ga, sm, lo, hi, outp);
+    if constexpr (Sh::NC == 3) {
+      if (!bad && jr(1, lo, hi)) {
+        bad = run_block<S, P, Real, 0, 1>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 1, 1>(ga, sm, lo, hi, outp);
+      }
+      if (!bad && jr(2, lo, hi)) {
+        bad = run_block<S, P, Real, 0, 2>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 1, 2>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 2, 2>(ga, sm, lo, hi, outp);
+      }
+    }
+    if (bad) {
+      // element with det J <= 0: its whole output is zero (every slab group does its part)
+      auto colstart = [&](int slab) {   // first column J of a slab
+        int b = 0, j3 = slab;
+#pragma unroll
+        for (int c = 0; c < Sh::NC - 1; ++c)
+          if (b == c && j3 >= Sh::R(c, 2)) { j3 -= Sh::R(c, 2); b = c + 1; }
+        int r12 = Sh::R(0, 0) * Sh::R(0, 1), offb = 0;
+#pragma unroll
+        for (int c = 1; c < Sh::NC; ++c)
+          if (b == c) { r12 = Sh::R(c, 0) * Sh::R(c, 1); offb = Sh::OFF(c); }
+        return int64_t(offb) + int64_t(r12) * j3;
+      };
+      const int64_t J0 = colstart(s_lo);
+      const int64_t J1 = s_hi == Sh::NSLAB ? int64_t(Sh::OFF(Sh::NC)) : colstart(s_hi);
+      for (int64_t i = J0 * (J0 + 1) / 2 + tid; i < J1 * (J1 + 1) / 2; i += NTHREADS) outp[i] = Real(0);
+    }
+    if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
+  };
+  if constexpr (LISTED) {
+    // a listed launch: the item count and the first list entry come from the device,
+    // and the workgroups stride over the (item, slab group) pairs
+    const int64_t n_items = ga.list[0];
+    const int32_t* ids = ga.elem_ids + ga.list[1];
+    for (int64_t blk = blockIdx.x; blk < n_items * ngroups; blk += gridDim.x) {
+      run(blk, n_items, ids);
+      __syncthreads();   // the next item rewrites the shared buffers
+    }
+  } else {
+    run(blockIdx.x, ga.n_items, ga.elem_ids);   // one workgroup per (item, slab group)
   }
-  if (ga.status && tid == 0 && (bad || s_lo == 0)) ga.status[e] = bad ? -4 : 0;
 }
 
-template <int S, int P, typename Real>
+// One (space, p, precision): a plain launch (split into launches under the
+// dispatch limits) or, with LISTED, one listed launch of a fixed grid.
+template <int S, int P, typename Real, bool LISTED>
 hipError_t launch_general_one(const GeneralArgs& a, hipStream_t st) {
   constexpr int NS = Shape<S, P>::NSLAB;
   GeneralArgs c = a;
   c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
   if (c.diag_inline < 0 || !diag_inline_ok(S, P)) c.diag_inline = diag_inline_ok(S, P) ? 1 : 0;
   const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
-  const int64_t max_items = launch_items(ngroups);
-  for (int64_t base = 0; base < a.n_items; base += max_items) {
-    c.item_base = a.item_base + base;
-    c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
-    hipLaunchKernelGGL((k_general<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NTHREADS), 0, st, c);
+  if constexpr (LISTED) {
+    hipLaunchKernelGGL((k_general<S, P, Real, true>), dim3(list_grid(a.n_items, ngroups)), dim3(NTHREADS), 0, st, c);
+  } else {
+    const int64_t max_items = launch_items(ngroups);
+    for (int64_t base = 0; base < a.n_items; base += max_items) {
+      c.item_base = a.item_base + base;
+      c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
+      hipLaunchKernelGGL((k_general<S, P, Real, false>), dim3(unsigned(c.n_items * ngroups)), dim3(NTHREADS), 0, st,
+                         c);
+    }
   }
   return hipGetLastError();
 }
 
-template <int S, typename Real>
+template <int S, typename Real, bool LISTED>
 hipError_t dispatch_general_p(int p, const GeneralArgs& a, hipStream_t st) {
   switch (p) {
-    case 1: return launch_general_one<S, 1, Real>(a, st);
-    case 2: return launch_general_one<S, 2, Real>(a, st);
-    case 3: return launch_general_one<S, 3, Real>(a, st);
-    case 4: return launch_general_one<S, 4, Real>(a, st);
-    case 5: return launch_general_one<S, 5, Real>(a, st);
-    case 6: return launch_general_one<S, 6, Real>(a, st);
-    case 7: return launch_general_one<S, 7, Real>(a, st);
-    case 8: return launch_general_one<S, 8, Real>(a, st);
-    case 9: return launch_general_one<S, 9, Real>(a, st);
-    case 10: return launch_general_one<S, 10, Real>(a, st);
-    case 11: return launch_general_one<S, 11, Real>(a, st);
+    case 1: return launch_general_one<S, 1, Real, LISTED>(a, st);
+    case 2: return launch_general_one<S, 2, Real, LISTED>(a, st);
+    case 3: return launch_general_one<S, 3, Real, LISTED>(a, st);
+    case 4: return launch_general_one<S, 4, Real, LISTED>(a, st);
+    case 5: return launch_general_one<S, 5, Real, LISTED>(a, st);
+    case 6: return launch_general_one<S, 6, Real, LISTED>(a, st);
+    case 7: return launch_general_one<S, 7, Real, LISTED>(a, st);
+    case 8: return launch_general_one<S, 8, Real, LISTED>(a, st);
+    case 9: return launch_general_one<S, 9, Real, LISTED>(a, st);
+    case 10: return launch_general_one<S, 10, Real, LISTED>(a, st);
+    case 11: return launch_general_one<S, 11, Real, LISTED>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int S>
+// Plain launches (LISTED = false) and listed ones are instantiated in separate files,
+// so the build compiles them in parallel.
+template <int S, bool LISTED>
 hipError_t dispatch_general(int p, int prec, const GeneralArgs& a, hipStream_t st) {
-  return prec ? dispatch_general_p<S, float>(p, a, st) : dispatch_general_p<S, double>(p, a, st);
+  return prec ? dispatch_general_p<S, float, LISTED>(p, a, st) : dispatch_general_p<S, double, LISTED>(p, a, st);
 }
 
 }  // namespace dpg

@@ -5,7 +5,7 @@
 namespace dpg {
 
 hipError_t launch_general_h1(int p, int prec, const GeneralArgs& a, hipStream_t s) {
-  return dispatch_general<SP_H1>(p, prec, a, s);
+  return dispatch_general<SP_H1, false>(p, prec, a, s);
 }
 
 }  // namespace dpg

@@ -5,7 +5,7 @@
 namespace dpg {
 
 hipError_t launch_general_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s) {
-  return dispatch_general<SP_HDIV>(p, prec, a, s);
+  return dispatch_general<SP_HDIV, false>(p, prec, a, s);
 }
 
 }  // namespace dpg

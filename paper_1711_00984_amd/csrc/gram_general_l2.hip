@@ -5,7 +5,7 @@
 namespace dpg {
 
 hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t s) {
-  return dispatch_general<SP_L2>(p, prec, a, s);
+  return dispatch_general<SP_L2, false>(p, prec, a, s);
 }
 
 }  // namespace dpg

@@ -41,7 +41,17 @@ struct GeneralArgs {
   int slab_group;            // column slabs per workgroup (0: choose from the batch size)
   int diag_inline;           // diagonal pairs: -1 default for the order, 0 last with the
                              // triangular x tiling, 1 each closing its slab (full x tiling)
+  const int32_t* list;       // listed launch: {item count, first entry in elem_ids} in device
+                             // memory (nullptr: n_items and elem_ids as given)
 };
+
+// Workgroups of a listed launch (the item count is on the device): enough to fill the
+// GPU several times over, each striding over the (item, slab group) pairs.
+constexpr int64_t LIST_GRID = 2048;
+inline unsigned list_grid(int64_t expected_items, int ngroups) {
+  const int64_t w = expected_items * ngroups;
+  return unsigned(w < 1 ? 1 : (w < LIST_GRID ? w : LIST_GRID));
+}
 
 // Column slabs per workgroup: whole elements when the batch alone fills the GPU
 // (about WG_TARGET workgroups), smaller groups for small batches.
@@ -59,6 +69,11 @@ hipError_t launch_general_h1(int p, int prec, const GeneralArgs& a, hipStream_t 
 hipError_t launch_general_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_general_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_general_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
+// The same with a listed launch (GeneralArgs::list set).
+hipError_t launch_general_list_h1(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_list_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_list_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_general_list_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
 
 // Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
 hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);

@@ -93,6 +93,11 @@ _lib.dpg_gram_integrate.restype = _i
 _lib.dpg_gram_integrate_batched.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
                                             ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate_batched.restype = _i
+_lib.dpg_gram_integrate_batched_noalloc.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
+                                                    ctypes.POINTER(Opts), _vp]
+_lib.dpg_gram_integrate_batched_noalloc.restype = _i
+_lib.dpg_noalloc_max_elements.argtypes = []
+_lib.dpg_noalloc_max_elements.restype = _i64
 _lib.dpg_autotune.argtypes = [_vp, _i, _i, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp,
                               ctypes.POINTER(ctypes.c_int)]
 _lib.dpg_autotune.restype = _i
@@ -412,6 +417,24 @@ class Context:
                                                out_offset.data_ptr(), out.data_ptr(), ctypes.byref(o),
                                                _stream_ptr(stream)))
         return out
+
+    def gram_batched_noalloc(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
+                             w0=1.0, w1=1.0, status=None, stream=None):
+        """The uneven batch without allocation (dpg_gram_integrate_batched_noalloc);
+        arguments as gram_batched."""
+        g = _geometry(geom, kind)
+        for t, dt in ((space, torch.int8), (p, torch.int8), (out_offset, torch.int64)):
+            if not (t.is_cuda and t.dtype == dt and t.numel() == g.n_elem):
+                raise ValueError("space/p must be int8 and out_offset int64 CUDA tensors of length n_elem")
+        o = _opts(prec, path, 0, w0, w1, status)
+        _check(_lib.dpg_gram_integrate_batched_noalloc(self._h, space.data_ptr(), p.data_ptr(), ctypes.byref(g),
+                                                       out_offset.data_ptr(), out.data_ptr(), ctypes.byref(o),
+                                                       _stream_ptr(stream)))
+        return out
+
+
+def noalloc_max_elements():
+    return int(_lib.dpg_noalloc_max_elements())
 
 
 class Server:
