@@ -107,6 +107,9 @@ constexpr int NTHREADS = 256;
 #ifndef DPG_MINW2_LMAX
 #define DPG_MINW2_LMAX 8
 #endif
+#ifndef DPG_YTAIL_VALU
+#define DPG_YTAIL_VALU 1
+#endif
 constexpr int ru16(int x) { return (x + 15) / 16 * 16; }
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
@@ -145,6 +148,12 @@ template <int S, int P, int A, int B> struct Blk {
   static constexpr int R1a = Sh::R(A, 0), R1b = Sh::R(B, 0), R2a = Sh::R(A, 1), R2b = Sh::R(B, 1);
   static constexpr int R3a = Sh::R(A, 2), R3b = Sh::R(B, 2);
   static constexpr int NY = R1a * R1b, NYT = (NY + 15) / 16;
+  // y tail: when the last y-tile would hold at most a quarter of its 16 columns, those
+  // y = (i1, j1) are summed on the VALU from the stage-2 accumulators instead of
+  // through a padded MFMA tile; NYM y-tiles remain on MFMA
+  static constexpr int YTAIL = NY % 16;
+  static constexpr bool YV = DPG_YTAIL_VALU && NY > 16 && YTAIL != 0 && YTAIL <= 4;
+  static constexpr int NYM = YV ? NY / 16 : NYT;
   static constexpr int NX = R2a * R2b, NXT = (NX + 15) / 16;
   static constexpr int NXD = R2a * (R2a + 1) / 2, NXDT = (NXD + 15) / 16;
   static constexpr int NG = make_plan(S, A, B).ng;
@@ -429,7 +438,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   constexpr int XT = DIAG ? BC::NXDT : BC::NXT;
   constexpr int NXv = DIAG ? BC::NXD : BC::NX;
   constexpr bool C2 = Cache2<S, P, Real, A, B>::ON && !DIAG;
-  constexpr int YB = imin(DPG_YB, BC::NYT), YCH = (BC::NYT + YB - 1) / YB;
+  constexpr int YB = imin(DPG_YB, BC::NYM), YCH = (BC::NYM + YB - 1) / YB;
   const Real* sT = static_cast<const Real*>(sm.T);
   const Real* sU1 = static_cast<const Real*>(sm.U1);
   const int tid = threadIdx.x;
@@ -519,7 +528,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
           const Real a = acc2[g][pi * RPP + rho];
           static_for<YB>([&](auto YY) {
             constexpr int yt = yc * YB + decltype(YY)::value;
-            if constexpr (yt < BC::NYT) {
+            if constexpr (yt < BC::NYM) {
               Real u;
               if constexpr (Cache1<S, P, A, B>::ON) {
                 u = rg.u1[(g * RPP + rho) * BC::NYT + yt];
@@ -550,7 +559,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
       const int Ib = Ibp[pi], Jb = Jbp[pi];
       static_for<YB>([&](auto YY) {
         constexpr int yt = yc * YB + decltype(YY)::value;
-        if constexpr (yt < BC::NYT) {
+        if constexpr (yt < BC::NYM) {
           const int y = yt * 16 + lr;
           const int i1 = y % BC::R1a, j1 = y / BC::R1a;
           const unsigned ya8 = y < BC::NY ? unsigned((Ib + i1) * int(sizeof(Real))) : kDropOff;
@@ -650,6 +659,49 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
           mm(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
           st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
           if constexpr (sp % YCH == YCH - 1) flush(std::integral_constant<int, sp / YCH>{});
+        }
+      });
+    }
+    // ---------------- y tail on the VALU ----------------
+    // G[x][y] for the block's last YTAIL y: each lane sums its share of k = (g, l = 4 rho + lk)
+    // of the stage-1 contraction from the stage-2 accumulator, and two exchanges between lane
+    // groups (xor 16, 32) complete the sum, so every lane group holds G[x = xt*16 + arow(lr)][y].
+    // Lane group lk then stores the lk-th tail y, with the masks of the MFMA tiles' stores.
+    if constexpr (BC::YV) {
+      static_assert(!CF::HD, "held column heads need whole y-tiles");
+      const int xs = xt * 16 + M::arow(lr);
+      int i2 = 0, j2 = 0;
+      if (xs < NXv) decode_x<BC::R2a, DIAG>(sm.xd, xs, i2, j2);
+      const int yl = BC::NYM * 16 + lk;
+      const int i1 = yl % BC::R1a, j1 = yl / BC::R1a;
+      const int il = i1 + BC::R1a * i2, jl = j1 + BC::R1b * j2;
+      const bool ok = xs < NXv && lk < BC::YTAIL && (!DIAG || i2 < j2 || i1 <= j1);
+      static_for<NP>([&](auto PI) {
+        constexpr int pi = decltype(PI)::value;
+        if (pi < npg) {
+          Real v = Real(0);
+          static_for<BC::YTAIL>([&](auto TT) {
+            constexpr int t = decltype(TT)::value;
+            constexpr int y = BC::NYM * 16 + t, ti1 = y % BC::R1a, tj1 = y / BC::R1a;
+            Real sum = Real(0);
+            static_for<BC::NG>([&](auto G) {
+              constexpr int g = decltype(G)::value;
+              constexpr int r1 = BC::PL.gr1[g], s1 = BC::PL.gs1[g];
+              static_for<RPP>([&](auto RHO) {
+                constexpr int rho = decltype(RHO)::value;
+                const Real u = sT[r1 * KTL + (ti1 + Sh::SH(A, 0)) * L + lk + 4 * rho] *
+                               sT[s1 * KTL + (tj1 + Sh::SH(B, 0)) * L + lk + 4 * rho];
+                sum += acc2[g][pi * RPP + rho] * u;
+              });
+            });
+            sum += __shfl_xor(sum, 16);
+            sum += __shfl_xor(sum, 32);
+            if (lk == t) v = sum;
+          });
+          const unsigned J = unsigned(Jbp[pi] + jl);
+          const unsigned off = (unsigned(Ibp[pi] + il) + ((__umul24(J, J) + J) >> 1)) * unsigned(sizeof(Real));
+          const bool keep = ok && (!dgp[pi] || il <= jl);
+          store_out(v, rsrc, int(keep ? off : kDropOff));
         }
       });
     }
