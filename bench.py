@@ -134,8 +134,9 @@ def main():
     ap.add_argument("--no-extra", dest="extra", action="store_false")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="length of the replayed serving trace (0: skip the serving measurement)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="measured length of the replayed serving trace, after a 5 s warm-up "
+                         "(0: skip the serving measurement)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 4 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -217,6 +218,7 @@ def main():
     if a.extra:
         extra["batched_mixed_50000"] = run_mixed_full(ctx, dpg, stream)
         extra["scaling"] = run_scaling(ctx, dpg, stream)
+        extra["latency"] = run_latency(ctx, dpg, stream)
     serving = None
     if a.serve_seconds > 0:
         serving = run_serving(ctx, dpg, a.serve_seconds)
@@ -263,26 +265,7 @@ def run_extra(ctx, dpg, stream, E, X, out64):
     torch.cuda.empty_cache()
     log(f"[bench] extra fp32: {res['h1_p7_fp32']}")
 
-    aff = []
-    for space in ("HCURL", "HDIV"):
-        for p, n_e in ((4, 20000), (6, 4000), (8, 1000)):
-            A = torch.from_numpy(meshgen.affine_parallelepipeds(n_e, seed=1713)).cuda()
-            mm = dpg.packed_len(space, p)
-            o = torch.empty(n_e * mm, dtype=torch.float64, device="cuda")
-            row = {"space": space, "p": p, "n_elem": n_e}
-            for path in ("reduced", "general"):
-                ctx.autotune(space, p, A, kind="affine", out=o, path=path, stream=stream)
-                w, pr = time_launches(lambda: ctx.gram(space, p, A, kind="affine", out=o, path=path,
-                                                       stream=stream), 5, 1, stream)
-                kk = float(np.mean(pr))
-                row[path] = {"elements_per_s": round(n_e * 5 / w, 1), "kernel_ms": round(kk, 4),
-                             "hbm_gbs": round((mm * 8 + 96) * n_e / (kk * 1e-3) / 1e9, 1),
-                             "hbm_frac": round((mm * 8 + 96) * n_e / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-            aff.append(row)
-            log(f"[bench] extra affine {row}")
-            del o, A
-            torch.cuda.empty_cache()
-    res["affine_reduced_vs_general"] = aff
+    res["affine_reduced_vs_general"] = run_config3(ctx, dpg, stream)
 
     # extruded elements (quadrilaterals extruded along x1): reduced (exact xi1 integrals) vs general
     ext = []
@@ -405,6 +388,126 @@ def run_extra(ctx, dpg, stream, E, X, out64):
     return res
 
 
+def run_config3(ctx, dpg, stream, n_elem=20000, chunk_bytes=48 << 30, n_check=6):
+    """20,000 affine parallelepipeds (J = (I + S) diag(lam), seed 1713), H(curl) and
+    H(div) at p = 4, 6, 8: the reduced O(p^6) path and the general O(p^7) path at the
+    full element count.  Outputs above chunk_bytes (p = 8: 302 / 239 GB) run as
+    consecutive element chunks through two reused buffers; before a chunk's buffers
+    are reused, n_check of its elements are compared between the two paths
+    (max |reduced - general| <= 1e-12 max |reduced|; both are pinned to the oracle by
+    the tests).  Kernel times are event-timed per chunk and summed."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    A_all = meshgen.affine_parallelepipeds(n_elem, seed=1713)
+    rows = []
+    for space in ("HCURL", "HDIV"):
+        for p in (4, 6, 8):
+            mm = dpg.packed_len(space, p)
+            per = max(1, min(n_elem, chunk_bytes // (mm * 8)))
+            bufs = {k: torch.empty(per * mm, dtype=torch.float64, device="cuda") for k in ("reduced", "general")}
+            ms = {"reduced": 0.0, "general": 0.0}
+            worst = 0.0
+            chunks = 0
+            rng = np.random.default_rng(p)
+            for c0 in range(0, n_elem, per):
+                c1 = min(n_elem, c0 + per)
+                A = torch.from_numpy(np.ascontiguousarray(A_all[c0:c1])).cuda()
+                for path in ("reduced", "general"):
+                    ctx.gram(space, p, A, kind="affine", out=bufs[path], path=path, stream=stream)   # warm
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    ctx.gram(space, p, A, kind="affine", out=bufs[path], path=path, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms[path] += e0.elapsed_time(e1)
+                for e in rng.integers(0, c1 - c0, n_check):
+                    r = bufs["reduced"][e * mm:(e + 1) * mm]
+                    g = bufs["general"][e * mm:(e + 1) * mm]
+                    worst = max(worst, float((r - g).abs().max() / r.abs().max()))
+                chunks += 1
+                del A
+            assert worst <= 1e-12, f"config 3 {space} p={p}: reduced vs general {worst:.3e}"
+            out_b = float(mm * 8 + 96) * n_elem
+            row = {"space": space, "p": p, "n_elem": n_elem, "chunks": chunks, "output_gb": round(out_b / 1e9, 1),
+                   "sample_max_rel_diff": worst}
+            for path in ("reduced", "general"):
+                row[path] = {"kernel_ms": round(ms[path], 3), "elements_per_s": round(n_elem / (ms[path] * 1e-3), 1),
+                             "hbm_gbs": round(out_b / (ms[path] * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(out_b / (ms[path] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            rows.append(row)
+            log(f"[bench] config 3 {row}")
+            del bufs
+            torch.cuda.empty_cache()
+    return rows
+
+
+# The paper's own single-element timings (seconds per element; one element equal to the
+# master hexahedron; hardware, compiler and precision not stated), context only:
+# Table 1 (H1 Gram of the Poisson primal test space) and Table 3 (H(curl) Gram of the
+# Maxwell primal test space), tensorization and simplified tensorization columns.
+PAPER_SECONDS = {
+    ("H1", "tensorization"): {2: 1.64e-3, 3: 1.95e-3, 4: 3.31e-3, 5: 6.70e-3, 6: 1.49e-2, 7: 3.05e-2},
+    ("H1", "simplified"): {2: 1.67e-3, 3: 1.89e-3, 4: 2.85e-3, 5: 4.96e-3, 6: 9.45e-3, 7: 1.80e-2},
+    ("HCURL", "tensorization"): {2: 3.41e-2, 3: 3.98e-2, 4: 5.39e-2, 5: 9.42e-2, 6: 0.203, 7: 0.464},
+    ("HCURL", "simplified"): {2: 3.17e-2, 3: 3.32e-2, 4: 3.67e-2, 5: 5.02e-2, 6: 7.88e-2, 7: 0.132},
+}
+
+
+def run_latency(ctx, dpg, stream, reps=200):
+    """Single-element calls: config 1 (the cube (0,2)^3, H1, p = 3) and one element
+    equal to the master hexahedron (the paper's timing workload) for H1 and H(curl) at
+    p = 2..7, on the general path (trilinear input) and the reduced path (affine
+    identity).  Per call: the kernel time (events) and the host-side latency of the
+    call plus a stream synchronisation (median over reps), beside the paper's seconds
+    per element (Tables 1 and 3, hardware unstated) as context."""
+    import numpy as np
+    import torch
+
+    import meshgen
+
+    def timed(fn):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        k, h = [], []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            h.append(time.perf_counter() - t0)
+            k.append(e0.elapsed_time(e1))
+        return round(float(np.median(k)) * 1e3, 2), round(float(np.median(h)) * 1e6, 1)
+
+    out = {}
+    cube = torch.from_numpy(meshgen.scaled_cube(2.0)).cuda()
+    o = ctx.gram("H1", 3, cube)
+    k, h = timed(lambda: ctx.gram("H1", 3, cube, out=o, stream=stream))
+    out["config1_h1_p3_cube"] = {"kernel_us": k, "call_us_p50": h}
+    log(f"[bench] config 1 latency: kernel {k} us, call + sync {h} us")
+    unit = torch.from_numpy(meshgen.scaled_cube(1.0)).cuda()
+    ident = torch.zeros(12, dtype=torch.float64, device="cuda")
+    ident[3:] = torch.eye(3, dtype=torch.float64, device="cuda").reshape(-1)
+    rows = []
+    for space in ("H1", "HCURL"):
+        for p in range(2, 8):
+            o = ctx.gram(space, p, unit)
+            kg, hg = timed(lambda: ctx.gram(space, p, unit, out=o, stream=stream))
+            kr, hr = timed(lambda: ctx.gram(space, p, ident, kind="affine", out=o, stream=stream))
+            rows.append({"space": space, "p": p, "general_kernel_us": kg, "general_call_us": hg,
+                         "reduced_kernel_us": kr, "reduced_call_us": hr,
+                         "paper_tensorization_s": PAPER_SECONDS[(space, "tensorization")][p],
+                         "paper_simplified_s": PAPER_SECONDS[(space, "simplified")][p]})
+    out["identity_element"] = rows
+    out["paper_hardware"] = "not stated in the paper"
+    log(f"[bench] identity element rows: {rows}")
+    return out
+
+
 def run_scaling(ctx, dpg, stream, out_bytes=2 << 30):
     """Time per element against the order: the general path on perturbed hexes
     (H1) and the reduced path on affine elements (H(curl)), p = 2..11, FP64,
@@ -471,12 +574,14 @@ def run_mixed_full(ctx, dpg, stream, n_elem=50000, chunk_bytes=48 << 30):
             chunks.append((torch.from_numpy(sp[a0:a1].copy()).cuda(), torch.from_numpy(pr_[a0:a1].copy()).cuda(),
                            torch.from_numpy(np.ascontiguousarray(G[a0:a1])).cuda(), torch.from_numpy(off).cuda(),
                            int(lens[a0:a1].sum())))
+        host = [(np.ascontiguousarray(sp[a0:a1]), np.ascontiguousarray(pr_[a0:a1])) for a0, a1 in cuts]
         buf = torch.empty(max(c[4] for c in chunks), dtype=torch.float64 if es == 8 else torch.float32,
                           device="cuda")
 
         def one_pass():
-            for s_, p_, g_, o_, _ in chunks:
-                ctx.gram_batched(s_, p_, g_, o_, buf, prec=prec, stream=stream)
+            # space/p from the host copies: a replayed plan is enqueued without reading them back
+            for (s_, p_, g_, o_, _), (hs, hp) in zip(chunks, host):
+                ctx.gram_batched_host(hs, hp, g_, o_, buf, prec=prec, stream=stream)
 
         one_pass()                      # plans (graph capture) and warm-up
         torch.cuda.synchronize()
@@ -494,32 +599,33 @@ def run_mixed_full(ctx, dpg, stream, n_elem=50000, chunk_bytes=48 << 30):
     return res
 
 
-def run_serving(ctx, dpg, seconds, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30):
+def run_serving(ctx, dpg, seconds, warmup=5.0, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30):
     """Replay a Poisson serving trace through the serving loop (dpg_serve_*).
 
     Requests: 64..2048 trilinear hexes, space uniform, p uniform in 2..10 plus
-    dp = 1, FP64, arriving at rate_hz for `seconds`.  The client submits each
-    request at its arrival time, split into element chunks of at most
-    chunk_bytes output (the server admits whole requests only, and a 2048-element
-    H(curl) p=11 request alone is 185 GB), polls, and releases each result as
+    dp = 1, FP64, arriving at rate_hz for warmup + seconds.  The client submits
+    each request at its arrival time with dpg_serve_submit_chunked: the server
+    cuts it into element chunks of at most chunk_bytes output (a 2048-element
+    H(curl) p = 11 request alone is 185 GB), polls, and releases each chunk as
     soon as it is complete.  Request latency = arrival -> last chunk pollable
-    (server clock); the server's own statistics are per chunk."""
+    (server clock), over the requests arriving after the warm-up; the server's
+    own statistics are per chunk and cover the whole trace."""
     import collections
 
     import numpy as np
     import torch
 
     import meshgen
-    trace = meshgen.serving_trace(duration_s=seconds, rate_hz=rate_hz, n_lo=64, n_hi=2048, p_lo=2, p_hi=10,
-                                  dp=1, seed=seed)
+    trace = meshgen.serving_trace(duration_s=warmup + seconds, rate_hz=rate_hz, n_lo=64, n_hi=2048, p_lo=2,
+                                  p_hi=10, dp=1, seed=seed)
     geo = [meshgen.perturbed_hexes(r["n_elem"], seed=r["seed"]).reshape(-1) for r in trace]
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(192 << 30, free - (24 << 30)))
     srv = dpg.Server(ctx, mem_budget_bytes=budget, max_slots=1 << 21, max_inflight=256, max_queue=1 << 16,
                      n_streams=4, max_merge=32)
-    # warm-up: every (space, order) once, so code-object loading is not in the trace
-    warm = [srv.submit(s, q, meshgen.perturbed_hexes(64, seed=1).reshape(-1), dp=1)
-            for s in range(4) for q in range(2, 11)]
+    # every (space, order) once, so code-object loading is not in the trace
+    warm = [srv.submit(sp, q, meshgen.perturbed_hexes(64, seed=1).reshape(-1), dp=1)
+            for sp in range(4) for q in range(2, 11)]
     pend = set(warm)
     while pend:
         for t in list(pend):
@@ -529,47 +635,40 @@ def run_serving(ctx, dpg, seconds, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30
     srv.reset_stats()
 
     offered = 0.0
-    backlog = collections.deque()           # (request index, chunk geometry) not yet accepted
+    backlog = collections.deque()           # requests not yet accepted (queue full)
     owner, left, t_done = {}, {}, {}
-    arrival_srv, first, lag = {}, {}, {}
+    arrival_srv, lag = {}, {}
     i = 0
     t0 = time.perf_counter()
     while i < len(trace) or backlog or owner:
         now = time.perf_counter() - t0
         while i < len(trace) and trace[i]["t"] <= now:
-            r = trace[i]
-            b1 = dpg.packed_len(r["space"], r["p"] + r["dp"]) * 8
-            per = max(1, chunk_bytes // b1)
-            n = r["n_elem"]
-            offered += n * b1
-            ch = [(i, geo[i][24 * a:24 * min(n, a + per)]) for a in range(0, n, per)]
-            left[i] = len(ch)
-            backlog.extend(ch)
+            backlog.append(i)
             i += 1
         while backlog:
-            ri, g = backlog[0]
+            ri = backlog[0]
             r = trace[ri]
             try:
-                t = srv.submit(r["space"], r["p"], g, dp=r["dp"])
+                first, k, _ = srv.submit_chunked(r["space"], r["p"], geo[ri], dp=r["dp"], max_chunk_bytes=chunk_bytes)
             except dpg.DpgError as e:
                 if e.code == dpg.EAGAIN:
                     break
                 raise
             backlog.popleft()
-            owner[t] = ri
-            if ri not in first:
-                # how late the client submitted the request's first chunk
-                first[ri] = t
-                lag[ri] = (time.perf_counter() - t0) - r["t"]
+            lag[ri] = (time.perf_counter() - t0) - r["t"]      # how late the client submitted
+            left[ri] = k
+            for t in range(first, first + k):
+                owner[t] = ri
+            if r["t"] >= warmup:
+                offered += r["n_elem"] * dpg.packed_len(r["space"], r["p"] + r["dp"]) * 8
         for t in list(owner):
             res = srv.poll(t)
             if res is None:
                 continue
             ri = owner.pop(t)
             assert res["status"] == dpg.OK
-            if first[ri] == t:
-                # arrival on the server clock: first chunk's t_submit minus the client's lag
-                arrival_srv[ri] = res["t_submit"] - lag[ri]
+            # arrival on the server clock: the chunk's t_submit minus the client's lag
+            arrival_srv.setdefault(ri, res["t_submit"] - lag[ri])
             t_done[ri] = max(t_done.get(ri, 0.0), res["t_done"])
             left[ri] -= 1
             srv.release(t)
@@ -578,12 +677,16 @@ def run_serving(ctx, dpg, seconds, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30
     wall = time.perf_counter() - t0
     assert not any(left.values())
     st = srv.stats()
-    lat = np.array([t_done[k] - arrival_srv[k] for k in range(len(trace))])
-    elems = sum(r["n_elem"] for r in trace)
-    span = max(t_done.values()) - min(arrival_srv.values())
+    meas = [k for k in range(len(trace)) if trace[k]["t"] >= warmup]
+    lat = np.array([t_done[k] - arrival_srv[k] for k in meas])
+    elems = sum(trace[k]["n_elem"] for k in meas)
+    out_b = sum(trace[k]["n_elem"] * dpg.packed_len(trace[k]["space"], trace[k]["p"] + trace[k]["dp"]) * 8
+                for k in meas)
+    span = max(t_done[k] for k in meas) - min(arrival_srv[k] for k in meas)
     out = {
-        "requests": len(trace), "rate_hz": rate_hz, "duration_s": seconds, "elements": elems,
-        "elements_per_s": round(elems / span, 1), "output_tb_per_s": round(st["bytes"] / span / 1e12, 3),
+        "requests": len(meas), "warmup_requests": len(trace) - len(meas), "rate_hz": rate_hz,
+        "duration_s": seconds, "warmup_s": warmup, "elements": elems,
+        "elements_per_s": round(elems / span, 1), "output_tb_per_s": round(out_b / span / 1e12, 3),
         "offered_tb_per_s": round(offered / seconds / 1e12, 3),
         "latency_p50_ms": round(1e3 * float(np.percentile(lat, 50, method="inverted_cdf")), 3),
         "latency_p99_ms": round(1e3 * float(np.percentile(lat, 99, method="inverted_cdf")), 3),
@@ -592,9 +695,9 @@ def run_serving(ctx, dpg, seconds, rate_hz=200.0, seed=1715, chunk_bytes=8 << 30
         "chunk_wait_p99_ms": round(1e3 * st["wait_p99"], 3),
         "chunks": st["completed"], "launches": st["launches"], "max_concurrent_launches": st["max_concurrent_launches"],
         "budget_gb": round(budget / 1e9, 1), "peak_admitted_gb": round(st["peak_admitted_bytes"] / 1e9, 1),
-        "client_submit_lag_p99_ms": round(1e3 * float(np.percentile(list(lag.values()), 99)), 3),
+        "client_submit_lag_p99_ms": round(1e3 * float(np.percentile([lag[k] for k in meas], 99)), 3),
         "wall_s": round(wall, 2),
-        "precision": "fp64", "chunk_gb": round(chunk_bytes / 1e9, 1),
+        "precision": "fp64", "chunk_gb": round(chunk_bytes / 1e9, 1), "chunking": "server (dpg_serve_submit_chunked)",
     }
     log(f"[bench] serving: {out}")
     srv.close()

@@ -134,7 +134,10 @@ void dpg_opts_default(dpg_opts* opts);
  * immutable afterwards; the context (tables, tuning table, batched-dispatch
  * cache) may be shared by threads and streams, and owns its device memory
  * until dpg_ctx_destroy, which must not run concurrently with other calls on
- * the context. */
+ * the context.  The context starts with the library's tuning table: the file
+ * named by the environment variable DPG_TUNE_TABLE (an empty value: none; a
+ * file that cannot be read or parsed fails the call with DPG_EINVAL), else
+ * tune_gfx950.json beside libdpg.so when it exists (see dpg_autotune). */
 int dpg_tables_build(int p_max, void* stream, dpg_ctx** ctx);
 int dpg_ctx_destroy(dpg_ctx* ctx);
 
@@ -152,7 +155,8 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
  * length geom->n_elem; p[e] in [1, ctx p_max]) and its packed matrix starts at
  * out + out_offset[e] (device int64, in elements of the output type; regions
  * must not overlap).  All elements share opts (precision, path, weights).
- * The host reads space/p (a device-to-host copy on stream, synchronised) to
+ * The host reads space/p (a device-to-host copy on stream, synchronised; see
+ * dpg_gram_integrate_batched_host for callers that hold them on the host) to
  * plan the launch: elements are bucketed by (space, p) and each bucket's
  * kernel is captured as an independent node of one HIP graph, so the buckets
  * run concurrently.  The instantiated graph is cached in the context (up to 8
@@ -162,6 +166,14 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
 int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
                                const dpg_geometry* geom, const int64_t* out_offset, void* out,
                                const dpg_opts* opts, void* stream);
+/* The same with space and p in HOST memory (int8[n_elem] each; the caller keeps
+ * them unchanged until the call returns): no device-to-host read and no
+ * synchronisation, so a replayed plan is only enqueued on stream (a new plan
+ * still uploads its element lists synchronously once).  The plan cache key
+ * holds these host pointers and a hash of their contents. */
+int dpg_gram_integrate_batched_host(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                                    const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                                    const dpg_opts* opts, void* stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): dpg_gram_integrate_batched
@@ -268,6 +280,8 @@ int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void*
                  void* stream, int* slab_group);
 int dpg_tune_save(const dpg_ctx* ctx, const char* path);
 int dpg_tune_load(dpg_ctx* ctx, const char* path);
+/* Forget every tuned schedule of the context (heuristic defaults from then on). */
+int dpg_tune_clear(dpg_ctx* ctx);
 /* Tuned slabs per workgroup for this case (reduced: 0 general path, 1 reduced
  * path on affine geometry, 2 on extruded geometry), 0 if untuned, -1 on bad
  * arguments. */
@@ -300,8 +314,9 @@ int dpg_batch_plans(const dpg_ctx* ctx);
  * The server owns each request's geometry copy from submit, and its output
  * from admission, until release.  Element e of a result is at
  * out + e * packed_len (packed 'U' layout as above).  A request whose output
- * exceeds the budget, or whose elements exceed the slots, is rejected at
- * submit (DPG_EINVAL): the client splits it into element chunks.  All calls
+ * exceeds the budget, or whose elements exceed the slots, is rejected by
+ * dpg_serve_submit (DPG_EINVAL); dpg_serve_submit_chunked splits it into
+ * element chunks instead.  All calls
  * are thread-safe (many submitters; one internal scheduler thread).
  * Timestamps are seconds since dpg_serve_create on a monotonic clock; latency
  * = t_done - t_submit (t_done is when the result became pollable). */
@@ -360,6 +375,20 @@ typedef struct {
 void dpg_serve_cfg_default(dpg_serve_cfg* cfg);  /* 1 GiB, 2^18 slots, 64, 4096, 4 streams, 32 */
 int dpg_serve_create(dpg_ctx* ctx, const dpg_serve_cfg* cfg, dpg_server** srv);
 int dpg_serve_submit(dpg_server* srv, const dpg_request* req, uint64_t* ticket);
+/* A request of any size: the server cuts it into consecutive element chunks of
+ * *chunk_elems elements (the last one shorter), as many as fit max_chunk_bytes
+ * of output (0: the memory budget) and the element slots, and queues them as
+ * requests with the consecutive tickets *first_ticket .. *first_ticket +
+ * *n_chunks - 1; chunk k holds elements [k * *chunk_elems, ...) of the request.
+ * Each chunk is polled, read and released like a request of its own; the
+ * chunks are admitted in order as memory frees up, so a request larger than
+ * the budget streams through it while the client releases the chunks it has
+ * read.  All chunks are queued, or none: DPG_EAGAIN when the queue or the
+ * element slots cannot take them all now, DPG_EINVAL when one element's output
+ * exceeds the chunk size or the chunks exceed max_queue.  chunk_elems may be
+ * NULL. */
+int dpg_serve_submit_chunked(dpg_server* srv, const dpg_request* req, int64_t max_chunk_bytes,
+                             uint64_t* first_ticket, int64_t* n_chunks, int64_t* chunk_elems);
 int dpg_serve_poll(dpg_server* srv, uint64_t ticket, dpg_result* res);
 /* Copy elements [first, first + count) of a finished result to dst (host or
  * device), asynchronously on stream.  Release the request only after the copy

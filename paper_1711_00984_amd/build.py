@@ -33,15 +33,32 @@ def sources():
     return out
 
 
-def _headers_mtime():
-    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    hs.append(os.path.join(ROOT, "include", "dpg.h"))
-    return max(os.path.getmtime(h) for h in hs)
+def _deps_mtime(src):
+    """Latest modification time of src and of every local header it includes, transitively
+    (quoted includes resolved in csrc/ and include/)."""
+    seen, todo, latest = set(), [src], 0.0
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.add(f)
+        latest = max(latest, os.path.getmtime(f))
+        with open(f, errors="replace") as fh:
+            for line in fh:
+                line = line.strip()
+                if line.startswith("#include") and '"' in line:
+                    name = line.split('"')[1]
+                    for d in (os.path.dirname(f), CSRC, os.path.join(ROOT, "include")):
+                        cand = os.path.normpath(os.path.join(d, name))
+                        if os.path.exists(cand):
+                            todo.append(cand)
+                            break
+    return latest
 
 
-def _compile(src, incremental=False, hdr_mtime=0.0):
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), hdr_mtime):
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(src):
         return obj, 0.0, ""
     cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
@@ -60,18 +77,17 @@ def build(verbose=True, jobs=None, incremental=False):
     source and every header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    hdr = _headers_mtime()
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, dt, msgs in ex.map(lambda f: _compile(f, incremental, hdr), srcs):
+        for obj, dt, msgs in ex.map(lambda f: _compile(f, incremental), srcs):
             objs.append(obj)
             if verbose and dt > 0:
                 print(f"  compiled {os.path.basename(obj)} in {dt:.1f}s", flush=True)
                 if msgs.strip():
                     print(msgs, flush=True)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -204,6 +204,11 @@ int dpg_tables_build(int p_max, void* stream, dpg_ctx** out) {
     delete c;
     return hip_fail(e, "table upload");
   }
+  const int tr = dpg::load_default_tune(c);
+  if (tr != DPG_OK) {
+    delete c;
+    return tr;
+  }
   *out = c;
   return DPG_OK;
 }

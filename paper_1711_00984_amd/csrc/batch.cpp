@@ -37,10 +37,15 @@ struct BatchPlan {
   int32_t* d_ids = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;   // recorded after every replay
   int nbuckets = 0;
   ~BatchPlan() {
-    // a replay of this graph may still be running on some stream
-    if (exec) (void)hipDeviceSynchronize();
+    // Replays of one executable graph run in launch order, so the last replay's event
+    // covers them all; only this plan's work is waited for, not the device.
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (d_ids) (void)hipFree(d_ids);
@@ -68,28 +73,21 @@ constexpr int kMaxPlans = 8;
 using dpg::fail;
 using dpg::hip_fail;
 
-extern "C" int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
-                                          const dpg_geometry* geom, const int64_t* out_offset, void* out,
-                                          const dpg_opts* opts, void* stream) {
-  dpg_opts o;
-  if (opts) o = *opts; else dpg_opts_default(&o);
-  int rc = dpg::check_common(ctx, geom, out, o);
-  if (rc) return rc;
+namespace dpg {
+
+// Plan (or find the cached plan of) the batch whose per-element space and order are
+// hs, hp (host copies) and replay it on st.  key_space, key_p: the caller's arrays,
+// part of the plan's key with the contents' hash.
+static int batched_run(const dpg_ctx* ctx, const int8_t* hs, const int8_t* hp, const void* space, const void* p,
+                       const dpg_geometry* geom, const int64_t* out_offset, void* out, const dpg_opts& o,
+                       hipStream_t st) {
   const int64_t n = geom->n_elem;
-  if (n == 0) return DPG_OK;
-  if (!space || !p || !out_offset) return fail(DPG_EINVAL, "space, p and out_offset are required");
-  if (n > int64_t(0x7fffffff)) return fail(DPG_EINVAL, "batch too large (%lld elements)", (long long)n);
-  if (o.nq != 0) return fail(DPG_EINVAL, "batched integration uses the default point counts (nq = 0)");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<int8_t> hs(n), hp(n);
-  hipError_t e = hipMemcpyAsync(hs.data(), space, n, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), p, n, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "reading space/p");
+  int rc = DPG_OK;
+  hipError_t e = hipSuccess;
   for (int64_t i = 0; i < n; ++i)
     if (!dpg::valid_space(hs[i]) || hp[i] < 1 || hp[i] > ctx->p_max)
       return fail(DPG_EINVAL, "element %lld: space=%d p=%d invalid", (long long)i, hs[i], hp[i]);
-  const uint64_t h = dpg::fnv1a(hs.data(), hp.data(), n);
+  const uint64_t h = dpg::fnv1a(hs, hp, n);
 
   std::shared_ptr<dpg::BatchPlan> plan;
   {
@@ -160,14 +158,61 @@ extern "C" int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* spac
     if (e != hipSuccess) return hip_fail(e, "graph capture");
     e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    e = hipEventCreateWithFlags(&q->done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     plan = q;
+    std::vector<std::shared_ptr<dpg::BatchPlan>> evicted;   // destroyed after the lock is released
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->plans.push_back(q);
-    while (int(ctx->plans.size()) > dpg::kMaxPlans) ctx->plans.erase(ctx->plans.begin());
+    while (int(ctx->plans.size()) > dpg::kMaxPlans) {
+      evicted.push_back(ctx->plans.front());
+      ctx->plans.erase(ctx->plans.begin());
+    }
   }
   e = hipGraphLaunch(plan->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(plan->done, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return DPG_OK;
+}
+
+static int batched_check(const dpg_ctx* ctx, const int8_t* space, const int8_t* p, const dpg_geometry* geom,
+                         const int64_t* out_offset, void* out, const dpg_opts& o) {
+  int rc = dpg::check_common(ctx, geom, out, o);
+  if (rc) return rc;
+  const int64_t n = geom->n_elem;
+  if (n > 0 && (!space || !p || !out_offset)) return fail(DPG_EINVAL, "space, p and out_offset are required");
+  if (n > int64_t(0x7fffffff)) return fail(DPG_EINVAL, "batch too large (%lld elements)", (long long)n);
+  if (o.nq != 0) return fail(DPG_EINVAL, "batched integration uses the default point counts (nq = 0)");
+  return DPG_OK;
+}
+
+}  // namespace dpg
+
+extern "C" int dpg_gram_integrate_batched(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                                          const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                                          const dpg_opts* opts, void* stream) {
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  const int rc = dpg::batched_check(ctx, space, p, geom, out_offset, out, o);
+  if (rc || geom->n_elem == 0) return rc;
+  const int64_t n = geom->n_elem;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int8_t> hs(n), hp(n);
+  hipError_t e = hipMemcpyAsync(hs.data(), space, n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), p, n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "reading space/p");
+  return dpg::batched_run(ctx, hs.data(), hp.data(), space, p, geom, out_offset, out, o, st);
+}
+
+extern "C" int dpg_gram_integrate_batched_host(const dpg_ctx* ctx, const int8_t* space, const int8_t* p,
+                                               const dpg_geometry* geom, const int64_t* out_offset, void* out,
+                                               const dpg_opts* opts, void* stream) {
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  const int rc = dpg::batched_check(ctx, space, p, geom, out_offset, out, o);
+  if (rc || geom->n_elem == 0) return rc;
+  return dpg::batched_run(ctx, space, p, space, p, geom, out_offset, out, o, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int dpg_batch_plans(const dpg_ctx* ctx) {

@@ -85,6 +85,9 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
 int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, hipStream_t st);
 
+// Load the tuning table shipped with the library (dpg_tables_build).
+int load_default_tune(dpg_ctx* ctx);
+
 // Schedule from the tuning table (defaults when not tuned).
 Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int64_t n);
 

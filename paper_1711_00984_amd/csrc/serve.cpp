@@ -293,6 +293,13 @@ int dpg_serve_submit(dpg_server* srv, const dpg_request* req, uint64_t* ticket) 
   return srv->s->submit(*req, ticket);
 }
 
+int dpg_serve_submit_chunked(dpg_server* srv, const dpg_request* req, int64_t max_chunk_bytes, uint64_t* first_ticket,
+                             int64_t* n_chunks, int64_t* chunk_elems) {
+  if (!srv) return fail(DPG_ENOTINIT, "null server");
+  if (!req) return fail(DPG_EINVAL, "request is NULL");
+  return srv->s->submit_chunked(*req, max_chunk_bytes, first_ticket, n_chunks, chunk_elems);
+}
+
 int dpg_serve_poll(dpg_server* srv, uint64_t ticket, dpg_result* res) {
   if (!srv) return fail(DPG_ENOTINIT, "null server");
   return srv->s->poll(ticket, res);

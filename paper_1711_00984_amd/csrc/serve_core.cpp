@@ -100,29 +100,20 @@ double Server::now() const {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
 }
 
-int Server::submit(const dpg_request& rq, uint64_t* ticket) {
-  const double t_submit = now();
-  if (!ticket) return fail(DPG_EINVAL, "ticket pointer is NULL");
-  *ticket = 0;
-  auto reject = [&](int code) {
-    std::lock_guard<std::mutex> lk(mu_);
-    ++st_rejected_;
-    return code;
-  };
-  if (rq.space < DPG_H1 || rq.space > DPG_L2) return reject(fail(DPG_EINVAL, "unknown space %d", rq.space));
+int Server::prepare(const dpg_request& rq, Req& r, double t_submit) {
+  if (rq.space < DPG_H1 || rq.space > DPG_L2) return fail(DPG_EINVAL, "unknown space %d", rq.space);
   if (rq.p < 1 || rq.dp < 0 || rq.p + rq.dp > p_max_)
-    return reject(fail(DPG_EINVAL, "p=%d dp=%d: Gram order outside [1, %d]", rq.p, rq.dp, p_max_));
-  if (rq.prec != DPG_FP64 && rq.prec != DPG_FP32) return reject(fail(DPG_EINVAL, "unknown precision %d", rq.prec));
-  if (rq.path < DPG_PATH_AUTO || rq.path > DPG_PATH_REDUCED)
-    return reject(fail(DPG_EINVAL, "unknown path %d", rq.path));
+    return fail(DPG_EINVAL, "p=%d dp=%d: Gram order outside [1, %d]", rq.p, rq.dp, p_max_);
+  if (rq.prec != DPG_FP64 && rq.prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", rq.prec);
+  if (rq.path < DPG_PATH_AUTO || rq.path > DPG_PATH_REDUCED) return fail(DPG_EINVAL, "unknown path %d", rq.path);
   if (rq.geom.kind != DPG_GEOM_TRILINEAR && rq.geom.kind != DPG_GEOM_AFFINE && rq.geom.kind != DPG_GEOM_EXTRUDED)
-    return reject(fail(DPG_EINVAL, "unknown geometry kind %d", rq.geom.kind));
+    return fail(DPG_EINVAL, "unknown geometry kind %d", rq.geom.kind);
   if (rq.path == DPG_PATH_REDUCED && rq.geom.kind == DPG_GEOM_TRILINEAR)
-    return reject(fail(DPG_EINVAL, "the reduced path needs affine or extruded geometry"));
-  if (rq.geom.n_elem < 1 || !rq.geom.data) return reject(fail(DPG_EINVAL, "empty request or NULL geometry"));
-  if (!std::isfinite(rq.w0) || !std::isfinite(rq.w1)) return reject(fail(DPG_EINVAL, "weights must be finite"));
+    return fail(DPG_EINVAL, "the reduced path needs affine or extruded geometry");
+  if (rq.geom.n_elem < 1 || !rq.geom.data) return fail(DPG_EINVAL, "empty request or NULL geometry");
+  if (!std::isfinite(rq.w0) || !std::isfinite(rq.w1)) return fail(DPG_EINVAL, "weights must be finite");
   const int pr = rq.p + rq.dp;
-  Req r;
+  r = Req{};
   r.w.space = rq.space;
   r.w.p = pr;
   r.w.prec = rq.prec;
@@ -135,49 +126,132 @@ int Server::submit(const dpg_request& rq, uint64_t* ticket) {
   r.t_submit = t_submit;
   const double bytes = double(r.w.n) * double(r.w.packed_len) * elem_bytes(rq.prec);
   if (bytes > double(out_alloc_.capacity()))
-    return reject(fail(DPG_EINVAL, "request output (%.3g bytes) exceeds the memory budget (%lld bytes); split it",
-                       bytes, (long long)out_alloc_.capacity()));
+    return fail(DPG_EINVAL, "request output (%.3g bytes) exceeds the memory budget (%lld bytes); split it",
+                bytes, (long long)out_alloc_.capacity());
   if (r.w.n > slot_alloc_.capacity())
-    return reject(fail(DPG_EINVAL, "request of %lld elements exceeds the %lld element slots", (long long)r.w.n,
-                       (long long)slot_alloc_.capacity()));
+    return fail(DPG_EINVAL, "request of %lld elements exceeds the %lld element slots", (long long)r.w.n,
+                (long long)slot_alloc_.capacity());
   r.out_bytes = out_alloc_.round(int64_t(bytes));
   r.slots = r.w.n;
-  uint64_t t;
+  return DPG_OK;
+}
+
+int Server::enqueue(std::vector<Req>& rs, std::vector<dpg_request>& sub, uint64_t* first) {
+  const int64_t k = int64_t(rs.size());
+  uint64_t t0;
   {
     std::lock_guard<std::mutex> lk(mu_);
     if (stop_) return fail(DPG_ENOTINIT, "server is shutting down");
-    if (int64_t(queue_.size()) >= cfg_.max_queue) {
+    if (int64_t(queue_.size()) + k > cfg_.max_queue) {
       ++st_rejected_;
       return fail(DPG_EAGAIN, "queue full (%d requests)", cfg_.max_queue);
     }
-    const int64_t s0 = slot_alloc_.alloc(r.slots);
-    if (s0 < 0) {
-      ++st_rejected_;
-      return fail(DPG_EAGAIN, "no %lld free element slots", (long long)r.slots);
+    int64_t i = 0;
+    for (; i < k; ++i) {
+      const int64_t s0 = slot_alloc_.alloc(rs[i].slots);
+      if (s0 < 0) break;
+      rs[i].w.slot0 = s0;
     }
-    r.w.slot0 = s0;
-    t = next_ticket_++;
-    r.w.ticket = t;
-    r.state = QUEUED;
-    reqs_.emplace(t, r);   // not in queue_ yet: invisible to the scheduler until its geometry is on the device
+    if (i < k) {   // all or nothing
+      for (int64_t j = 0; j < i; ++j) slot_alloc_.release(rs[j].w.slot0, rs[j].slots);
+      ++st_rejected_;
+      return fail(DPG_EAGAIN, "no %lld free element slots", (long long)rs[i].slots);
+    }
+    t0 = next_ticket_;
+    next_ticket_ += uint64_t(k);
+    for (i = 0; i < k; ++i) {
+      rs[i].w.ticket = t0 + uint64_t(i);
+      rs[i].state = QUEUED;
+      reqs_.emplace(t0 + uint64_t(i), rs[i]);   // not in queue_ yet: invisible to the scheduler
+    }
   }
-  bool staged = false;
-  const int rc = ex_->put_geometry(rq, r.w.slot0, &staged);
+  // geometry into the slots, without the lock
+  int rc = DPG_OK;
+  std::vector<char> staged(size_t(k), 0);
+  for (int64_t i = 0; i < k && rc == DPG_OK; ++i) {
+    bool st = false;
+    rc = ex_->put_geometry(sub[size_t(i)], rs[size_t(i)].w.slot0, &st);
+    staged[size_t(i)] = st;
+  }
   {
     std::lock_guard<std::mutex> lk(mu_);
+    for (int64_t i = 0; i < k; ++i) {
+      const uint64_t t = t0 + uint64_t(i);
+      if (rc != DPG_OK) {
+        slot_alloc_.release(rs[size_t(i)].w.slot0, rs[size_t(i)].slots);
+        reqs_.erase(t);
+        continue;
+      }
+      reqs_.at(t).w.staged = staged[size_t(i)] != 0;
+      queue_.push_back(t);
+      ++st_submitted_;
+      if (st_first_submit_ < 0) st_first_submit_ = rs[size_t(i)].t_submit;
+    }
     if (rc != DPG_OK) {
-      slot_alloc_.release(r.w.slot0, r.slots);
-      reqs_.erase(t);
       ++st_rejected_;
       return rc;
     }
-    reqs_.at(t).w.staged = staged;
-    queue_.push_back(t);
-    ++st_submitted_;
-    if (st_first_submit_ < 0) st_first_submit_ = t_submit;
   }
   cv_.notify_one();
-  *ticket = t;
+  *first = t0;
+  return DPG_OK;
+}
+
+int Server::submit(const dpg_request& rq, uint64_t* ticket) {
+  const double t_submit = now();
+  if (!ticket) return fail(DPG_EINVAL, "ticket pointer is NULL");
+  *ticket = 0;
+  std::vector<Req> rs(1);
+  int rc = prepare(rq, rs[0], t_submit);
+  if (rc != DPG_OK) {
+    std::lock_guard<std::mutex> lk(mu_);
+    ++st_rejected_;
+    return rc;
+  }
+  std::vector<dpg_request> sub{rq};
+  return enqueue(rs, sub, ticket);
+}
+
+int Server::submit_chunked(const dpg_request& rq, int64_t max_chunk_bytes, uint64_t* first, int64_t* n_chunks,
+                           int64_t* chunk_elems) {
+  const double t_submit = now();
+  if (!first || !n_chunks) return fail(DPG_EINVAL, "ticket or chunk-count pointer is NULL");
+  *first = 0;
+  *n_chunks = 0;
+  if (max_chunk_bytes < 0) return fail(DPG_EINVAL, "negative chunk size");
+  auto reject = [&](int code) {
+    std::lock_guard<std::mutex> lk(mu_);
+    ++st_rejected_;
+    return code;
+  };
+  // one element's output against the cap (budget, or the caller's smaller chunk size)
+  dpg_request one = rq;
+  one.geom.n_elem = rq.geom.n_elem > 0 ? 1 : 0;
+  Req probe;
+  int rc = prepare(one, probe, t_submit);
+  if (rc != DPG_OK) return reject(rc);
+  const double per = double(probe.w.packed_len) * elem_bytes(rq.prec);
+  const double cap = max_chunk_bytes > 0 ? std::min(double(max_chunk_bytes), double(out_alloc_.capacity()))
+                                         : double(out_alloc_.capacity());
+  if (per > cap)
+    return reject(fail(DPG_EINVAL, "one element's output (%.3g bytes) exceeds the chunk size (%.3g bytes)", per, cap));
+  const int64_t ce = std::max<int64_t>(1, std::min<int64_t>(int64_t(cap / per), slot_alloc_.capacity()));
+  const int64_t n = rq.geom.n_elem, k = (n + ce - 1) / ce;
+  if (k > cfg_.max_queue)
+    return reject(fail(DPG_EINVAL, "%lld chunks exceed the queue (%d)", (long long)k, cfg_.max_queue));
+  const int64_t stride = rq.geom.kind == DPG_GEOM_TRILINEAR ? 24 : rq.geom.kind == DPG_GEOM_AFFINE ? 12 : 10;
+  std::vector<Req> rs(static_cast<size_t>(k));
+  std::vector<dpg_request> sub(static_cast<size_t>(k), rq);
+  for (int64_t i = 0; i < k; ++i) {
+    sub[size_t(i)].geom.data = rq.geom.data + i * ce * stride;
+    sub[size_t(i)].geom.n_elem = std::min(ce, n - i * ce);
+    rc = prepare(sub[size_t(i)], rs[size_t(i)], t_submit);
+    if (rc != DPG_OK) return reject(rc);
+  }
+  rc = enqueue(rs, sub, first);
+  if (rc != DPG_OK) return rc;
+  *n_chunks = k;
+  if (chunk_elems) *chunk_elems = ce;
   return DPG_OK;
 }
 

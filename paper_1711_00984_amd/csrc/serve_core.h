@@ -99,6 +99,10 @@ class Server {
   Server(const dpg_serve_cfg& cfg, int p_max, std::unique_ptr<Executor> ex);
   ~Server();
   int submit(const dpg_request& req, uint64_t* ticket);
+  // A request cut into element chunks whose output fits max_chunk_bytes (0: the budget),
+  // queued as consecutive tickets, all or none.
+  int submit_chunked(const dpg_request& req, int64_t max_chunk_bytes, uint64_t* first, int64_t* n_chunks,
+                     int64_t* chunk_elems);
   int poll(uint64_t ticket, dpg_result* res);
   int release(uint64_t ticket);
   int read(uint64_t ticket, int what, void* dst, int64_t first, int64_t count, void* stream);
@@ -117,6 +121,11 @@ class Server {
     double t_submit = 0, t_admit = 0, t_done = 0;
   };
 
+  // validate a request and size its reservations (no lock)
+  int prepare(const dpg_request& rq, Req& r, double t_submit);
+  // reserve slots and consecutive tickets for rs (all or none), copy each geometry
+  // (sub[i]) into its slots, then queue them in order; *first = the first ticket
+  int enqueue(std::vector<Req>& rs, std::vector<dpg_request>& sub, uint64_t* first);
   void loop();
   void complete_locked(int64_t id, int rc);
   bool sweep_locked();

@@ -13,11 +13,13 @@
 // the tuner times the candidates on the caller's data and records the
 // winner per batch-size class (floor(log2(n_elem))).  The table can be saved
 // to and loaded from a small JSON file keyed by the GPU architecture.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -48,12 +50,41 @@ Sched tuned_sched(const dpg_ctx* ctx, int space, int p, int prec, int path, int6
   return best;
 }
 
+// The tuning table shipped with the library: DPG_TUNE_TABLE names a file (an empty
+// value: none), else tune_gfx950.json next to libdpg.so.  A missing file leaves the
+// heuristic defaults.
+int load_default_tune(dpg_ctx* ctx) {
+  const char* env = std::getenv("DPG_TUNE_TABLE");
+  std::string path;
+  if (env) {
+    if (!*env) return DPG_OK;
+    path = env;
+  } else {
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void*>(&dpg_tune_load), &info) || !info.dli_fname) return DPG_OK;
+    path = info.dli_fname;
+    const size_t slash = path.rfind('/');
+    path = (slash == std::string::npos ? std::string() : path.substr(0, slash + 1)) + "tune_gfx950.json";
+  }
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return env ? fail(DPG_EINVAL, "DPG_TUNE_TABLE=%s: cannot read", path.c_str()) : DPG_OK;
+  std::fclose(f);
+  return dpg_tune_load(ctx, path.c_str());
+}
+
 }  // namespace dpg
 
 using dpg::fail;
 using dpg::hip_fail;
 
 extern "C" {
+
+int dpg_tune_clear(dpg_ctx* ctx) {
+  if (!ctx) return fail(DPG_ENOTINIT, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->tune.clear();
+  return DPG_OK;
+}
 
 int dpg_autotune(dpg_ctx* ctx, int space, int p, const dpg_geometry* geom, void* out, const dpg_opts* opts,
                  void* stream, int* slab_group) {

@@ -93,6 +93,9 @@ _lib.dpg_gram_integrate.restype = _i
 _lib.dpg_gram_integrate_batched.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
                                             ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate_batched.restype = _i
+_lib.dpg_gram_integrate_batched_host.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
+                                                 ctypes.POINTER(Opts), _vp]
+_lib.dpg_gram_integrate_batched_host.restype = _i
 _lib.dpg_gram_integrate_batched_noalloc.argtypes = [_vp, _vp, _vp, ctypes.POINTER(Geometry), _vp, _vp,
                                                     ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate_batched_noalloc.restype = _i
@@ -117,6 +120,8 @@ _lib.dpg_tune_save.argtypes = [_vp, ctypes.c_char_p]
 _lib.dpg_tune_save.restype = _i
 _lib.dpg_tune_load.argtypes = [_vp, ctypes.c_char_p]
 _lib.dpg_tune_load.restype = _i
+_lib.dpg_tune_clear.argtypes = [_vp]
+_lib.dpg_tune_clear.restype = _i
 _lib.dpg_tune_lookup.argtypes = [_vp, _i, _i, _i, _i, _i64]
 _lib.dpg_tune_lookup.restype = _i
 _lib.dpg_batch_plans.argtypes = [_vp]
@@ -127,6 +132,9 @@ _lib.dpg_serve_create.argtypes = [_vp, ctypes.POINTER(ServeCfg), ctypes.POINTER(
 _lib.dpg_serve_create.restype = _i
 _lib.dpg_serve_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)]
 _lib.dpg_serve_submit.restype = _i
+_lib.dpg_serve_submit_chunked.argtypes = [_vp, ctypes.POINTER(Request), _i64, ctypes.POINTER(_u64),
+                                          ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+_lib.dpg_serve_submit_chunked.restype = _i
 _lib.dpg_serve_poll.argtypes = [_vp, _u64, ctypes.POINTER(Result)]
 _lib.dpg_serve_poll.restype = _i
 _lib.dpg_serve_read.argtypes = [_vp, _u64, _vp, _i64, _i64, _vp]
@@ -256,12 +264,18 @@ def _opts(prec, path, nq, w0, w1, status):
 
 
 class Context:
-    """Device-resident 1D tables (dpg_tables_build)."""
+    """Device-resident 1D tables (dpg_tables_build).  tune_table: "default" keeps the
+    tuning table the library loads (tune_gfx950.json beside libdpg.so), None starts
+    from an empty table, a path replaces it by that file."""
 
-    def __init__(self, p_max=P_MAX, stream=None):
+    def __init__(self, p_max=P_MAX, stream=None, tune_table="default"):
         self._h = ctypes.c_void_p()
         _check(_lib.dpg_tables_build(p_max, _stream_ptr(stream), ctypes.byref(self._h)))
         self.p_max = p_max
+        if tune_table != "default":
+            _check(_lib.dpg_tune_clear(self._h))
+            if tune_table is not None:
+                _check(_lib.dpg_tune_load(self._h, str(tune_table).encode()))
 
     @property
     def handle(self):
@@ -418,6 +432,23 @@ class Context:
                                                _stream_ptr(stream)))
         return out
 
+    def gram_batched_host(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
+                          w0=1.0, w1=1.0, status=None, stream=None):
+        """Uneven batch with space/p as host int8 numpy arrays (dpg_gram_integrate_batched_host):
+        no read back from the device, no synchronisation on replays."""
+        import numpy as np
+        g = _geometry(geom, kind)
+        for t in (space, p):
+            if not (isinstance(t, np.ndarray) and t.dtype == np.int8 and t.flags.c_contiguous and t.size == g.n_elem):
+                raise ValueError("space/p must be contiguous int8 numpy arrays of length n_elem")
+        if not (out_offset.is_cuda and out_offset.dtype == torch.int64 and out_offset.numel() == g.n_elem):
+            raise ValueError("out_offset must be an int64 CUDA tensor of length n_elem")
+        o = _opts(prec, path, 0, w0, w1, status)
+        _check(_lib.dpg_gram_integrate_batched_host(self._h, space.ctypes.data, p.ctypes.data, ctypes.byref(g),
+                                                    out_offset.data_ptr(), out.data_ptr(), ctypes.byref(o),
+                                                    _stream_ptr(stream)))
+        return out
+
     def gram_batched_noalloc(self, space, p, geom, out_offset, out, kind="trilinear", prec="fp64", path="auto",
                              w0=1.0, w1=1.0, status=None, stream=None):
         """The uneven batch without allocation (dpg_gram_integrate_batched_noalloc);
@@ -475,6 +506,23 @@ class Server:
         tensor (host or device) of n_elem * 24 (trilinear), * 12 (affine) or
         * 10 (extruded) values, copied before this returns.  Raises DpgError (code EAGAIN when
         the queue or the element slots are full)."""
+        r = self._request(space, p, geom, dp, kind, prec, path, w0, w1)
+        t = _u64(0)
+        _check(_lib.dpg_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def submit_chunked(self, space, p, geom, dp=0, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0,
+                       max_chunk_bytes=0):
+        """Queue a request of any size cut into element chunks (dpg_serve_submit_chunked);
+        returns (first ticket, number of chunks, elements per chunk).  Chunk k has the
+        ticket first + k and holds elements [k * chunk_elems, ...)."""
+        r = self._request(space, p, geom, dp, kind, prec, path, w0, w1)
+        t, k, ce = _u64(0), _i64(0), _i64(0)
+        _check(_lib.dpg_serve_submit_chunked(self._h, ctypes.byref(r), int(max_chunk_bytes), ctypes.byref(t),
+                                             ctypes.byref(k), ctypes.byref(ce)))
+        return t.value, k.value, ce.value
+
+    def _request(self, space, p, geom, dp, kind, prec, path, w0, w1):
         kind = KINDS.get(kind, kind)
         per = GEOM_STRIDE.get(kind, 24)
         if isinstance(geom, torch.Tensor):
@@ -488,11 +536,8 @@ class Server:
             ptr, numel, on_host = geom.ctypes.data, geom.size, 1
         if numel % per:
             raise ValueError(f"geometry size {numel} is not a multiple of {per}")
-        r = Request(space_id(space), int(p), int(dp), {"fp64": FP64, "fp32": FP32}.get(prec, prec),
-                    PATHS.get(path, path), on_host, Geometry(kind, 0, numel // per, ptr), float(w0), float(w1))
-        t = _u64(0)
-        _check(_lib.dpg_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
-        return t.value
+        return Request(space_id(space), int(p), int(dp), {"fp64": FP64, "fp32": FP32}.get(prec, prec),
+                       PATHS.get(path, path), on_host, Geometry(kind, 0, numel // per, ptr), float(w0), float(w1))
 
     def poll(self, ticket):
         """None while pending; else a dict with status, space, p (Gram order), prec,

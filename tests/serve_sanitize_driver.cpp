@@ -2,7 +2,7 @@
 // address/undefined sanitizers by tests/test_serve_sanitize.py (CPU only: it
 // links the scheduler core with its timing stub, never the HIP executor).
 //
-// Four submitter threads and two pollers race on one server: submits (with
+// Four submitter threads and two pollers race on one server: submits, chunked ones among them (with
 // EAGAIN back-off), polls, cancellations of queued requests, releases and
 // statistics reads, with a merge limit and a small budget so that admission,
 // merging and deferral paths all run.  Exit code 0 = every invariant held.
@@ -70,6 +70,17 @@ int main() {
       r.w0 = r.w1 = 1.0;
       uint64_t t = 0;
       int rc;
+      if (i % 5 == 4) {   // a request cut into chunks of at most 3 elements, queued all or none
+        r.geom.n_elem = std::min<int64_t>(r.geom.n_elem, 24);
+        int64_t k = 0, ce = 0;
+        while ((rc = srv.submit_chunked(r, 3 * bytes1, &t, &k, &ce)) == DPG_EAGAIN)
+          std::this_thread::sleep_for(std::chrono::microseconds(50));
+        CHECK(rc == DPG_OK && t != 0 && ce == 3 && k == (r.geom.n_elem + 2) / 3);
+        submitted += int(k);
+        std::lock_guard<std::mutex> lk(mu);
+        for (int64_t j = 0; j < k; ++j) live.push_back(t + uint64_t(j));
+        continue;
+      }
       while ((rc = srv.submit(r, &t)) == DPG_EAGAIN) std::this_thread::sleep_for(std::chrono::microseconds(50));
       CHECK(rc == DPG_OK && t != 0);
       ++submitted;
@@ -132,7 +143,7 @@ int main() {
 
   dpg_serve_stats st{};
   srv.stats(&st);
-  CHECK(st.submitted == 4 * per_thread);
+  CHECK(st.submitted == submitted.load());
   // a request cancelled by the client may have finished between its poll and
   // the release: the server's counts decide which it was
   CHECK(st.completed + st.failed + st.cancelled == st.submitted);

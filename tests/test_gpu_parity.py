@@ -357,6 +357,42 @@ def test_batched_equals_single(ctx, dpg):
                 compare64(G, R, f"batched {name} p={p}")
 
 
+def test_batched_host_arrays_equal_device_arrays(ctx, dpg):
+    """dpg_gram_integrate_batched_host (space/p on the host, no read back) gives the
+    batched call's matrices bit for bit, also on a replay of its cached plan and after
+    the host arrays change in place (a new plan)."""
+    say("batched, host space/p")
+    space, pr, X = meshgen.mixed_batch(200, p_lo=1, p_hi=8, dp=1, seed=71)
+    lens = np.array([dpg.packed_len(int(s), int(p)) for s, p in zip(space, pr)])
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    X_d, off_d = torch.from_numpy(X).cuda(), torch.from_numpy(off).cuda()
+    ref = torch.empty(int(lens.sum()), dtype=torch.float64, device="cuda")
+    ctx.gram_batched(torch.from_numpy(space).cuda(), torch.from_numpy(pr).cuda(), X_d, off_d, ref)
+    got = torch.empty_like(ref)
+    n0 = ctx.batch_plans()
+    for rep in range(3):
+        got.fill_(float("nan"))
+        ctx.gram_batched_host(space, pr, X_d, off_d, got)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), rep
+    assert ctx.batch_plans() == min(8, n0 + 1)
+    sp2 = space.copy()
+    pr2 = pr.copy()
+    pr2[3] = 1 if pr2[3] != 1 else 2
+    lens2 = np.array([dpg.packed_len(int(s), int(p)) for s, p in zip(sp2, pr2)])
+    off2 = torch.from_numpy(np.concatenate([[0], np.cumsum(lens2)[:-1]]).astype(np.int64)).cuda()
+    ref2 = torch.empty(int(lens2.sum()), dtype=torch.float64, device="cuda")
+    got2 = torch.empty_like(ref2)
+    ctx.gram_batched(torch.from_numpy(sp2).cuda(), torch.from_numpy(pr2).cuda(), X_d, off2, ref2)
+    ctx.gram_batched_host(sp2, pr2, X_d, off2, got2)
+    torch.cuda.synchronize()
+    assert torch.equal(got2, ref2)
+    with pytest.raises(dpg.DpgError):
+        bad = pr.copy()
+        bad[0] = 12
+        ctx.gram_batched_host(space, bad, X_d, off_d, got)
+
+
 def test_slab_groups_bitwise_identical_and_autotune(ctx, dpg, tmp_path):
     """Every work decomposition computes each entry with the same operation
     sequence, so outputs are bitwise equal; the tuner's choice is one of them."""
@@ -374,7 +410,7 @@ def test_slab_groups_bitwise_identical_and_autotune(ctx, dpg, tmp_path):
         assert torch.equal(out, ref), space
     f = tmp_path / "tune.json"
     ctx.tune_save(f)
-    c2 = dpg.Context(p_max=11)
+    c2 = dpg.Context(p_max=11, tune_table=None)
     try:
         assert c2.tune_lookup("H1", 5, n_elem=64) == 0
         c2.tune_load(f)

@@ -183,6 +183,35 @@ def test_bad_element_flagged_in_served_result(ctx, dpg):
     srv.close()
 
 
+def test_chunked_request_larger_than_the_budget(ctx, dpg):
+    """A request four budgets large, submitted with dpg_serve_submit_chunked: the
+    server cuts it into element chunks, each chunk's matrices equal the same
+    elements integrated alone, bit for bit, and the chunks stream through the
+    budget as the client releases them."""
+    say("chunked request")
+    space, pr, n = "HDIV", 6, 700
+    per = dpg.packed_len(space, pr) * 8
+    budget = 200 * per + 4096
+    srv = dpg.Server(ctx, mem_budget_bytes=budget, max_slots=4096, n_streams=2)
+    try:
+        X = meshgen.perturbed_hexes(n, seed=88)
+        ref = alone(ctx, space, pr, X)
+        first, k, ce = srv.submit_chunked(space, pr - 1, X.reshape(-1), dp=1)
+        assert ce == 200 and k == 4
+        m = dpg.packed_len(space, pr)
+        for c in range(k):
+            t = first + c
+            r = drain(srv, [t])[t]
+            assert r["status"] == dpg.OK and r["n_elem"] == min(ce, n - c * ce)
+            got = srv.read(t)
+            torch.cuda.synchronize()
+            assert torch.equal(got, ref[c * ce * m:(c * ce + r["n_elem"]) * m]), c
+            srv.release(t)
+        assert srv.stats()["peak_admitted_bytes"] <= budget
+    finally:
+        srv.close()
+
+
 def test_short_poisson_trace(ctx, dpg):
     say("short Poisson trace")
     trace = meshgen.serving_trace(duration_s=0.5, rate_hz=200.0, n_lo=64, n_hi=512, p_lo=2, p_hi=6, seed=77)

@@ -306,3 +306,49 @@ def test_bad_config():
     with pytest.raises(dpg.DpgError) as e:
         dpg.Server(None)               # the device executor needs a context
     assert e.value.code == dpg.ENOTINIT
+
+
+def test_chunked_request_streams_through_a_small_budget():
+    """A request three and a half budgets large is cut into element chunks that fit
+    the budget; the chunks have consecutive tickets, cover the request in order,
+    and stream through as the client releases each one."""
+    per = req_bytes("HCURL", 6, 1)
+    budget = 100 * per + 1000
+    s = dpg.Server(None, test_executor=True, mem_budget_bytes=budget, test_bytes_per_s=1e13)
+    n = 350
+    first, k, ce = s.submit_chunked("HCURL", 5, geom(n), dp=1)
+    assert ce == budget // per == 100 and k == 4
+    got = drain(s, list(range(first, first + k)))
+    assert [got[first + i]["n_elem"] for i in range(k)] == [100, 100, 100, 50]
+    assert all(r["status"] == dpg.OK and r["p"] == 6 for r in got.values())
+    st = s.stats()
+    assert st["completed"] == 4 and st["elements"] == n and st["peak_admitted_bytes"] <= budget
+    # a smaller chunk size than the budget, and a request that fits one chunk
+    first, k, ce = s.submit_chunked("HCURL", 5, geom(n), dp=1, max_chunk_bytes=40 * per)
+    assert (k, ce) == (9, 40)
+    drain(s, list(range(first, first + k)))
+    first, k, ce = s.submit_chunked("L2", 3, geom(10), dp=1)
+    assert k == 1 and ce >= 10
+    drain(s, [first])
+    s.close()
+
+
+def test_chunked_request_all_or_none():
+    per = req_bytes("H1", 4, 1)
+    s = dpg.Server(None, test_executor=True, mem_budget_bytes=10 * per + 1024, max_queue=5, test_launch_s=0.05)
+    with pytest.raises(dpg.DpgError) as e:                       # more chunks than the queue ever holds
+        s.submit_chunked("H1", 3, geom(60), dp=1)
+    assert e.value.code == dpg.EINVAL
+    with pytest.raises(dpg.DpgError) as e:                       # one element larger than the chunk size
+        s.submit_chunked("H1", 3, geom(5), dp=1, max_chunk_bytes=per // 2)
+    assert e.value.code == dpg.EINVAL
+    busy = [s.submit("H1", 3, geom(10), dp=1) for _ in range(3)]   # the head runs, two wait
+    with pytest.raises(dpg.DpgError) as e:                       # 4 chunks, 3 free queue entries at most
+        s.submit_chunked("H1", 3, geom(40), dp=1)
+    assert e.value.code == dpg.EAGAIN
+    assert s.stats()["queued"] <= 2                              # nothing of the rejected request was queued
+    drain(s, busy)
+    first, k, _ = s.submit_chunked("H1", 3, geom(40), dp=1)
+    assert k == 4
+    drain(s, list(range(first, first + k)))
+    s.close()
