@@ -393,10 +393,12 @@ def test_batched_host_arrays_equal_device_arrays(ctx, dpg):
         ctx.gram_batched_host(space, bad, X_d, off_d, got)
 
 
-def test_slab_groups_bitwise_identical_and_autotune(ctx, dpg, tmp_path):
+def test_slab_groups_bitwise_identical_and_autotune(dpg, tmp_path):
     """Every work decomposition computes each entry with the same operation
-    sequence, so outputs are bitwise equal; the tuner's choice is one of them."""
+    sequence, so outputs are bitwise equal; the tuner's choice is one of them.
+    Runs on a context with an empty tuning table (not the shipped one)."""
     say("autotune / slab groups")
+    ctx = dpg.Context(p_max=11, tune_table=None)
     X = torch.from_numpy(meshgen.perturbed_hexes(64, seed=3)).cuda()
     for space, p in (("H1", 5), ("HCURL", 3), ("HDIV", 4), ("L2", 5)):
         ref = ctx.gram(space, p, X)
@@ -419,6 +421,7 @@ def test_slab_groups_bitwise_identical_and_autotune(ctx, dpg, tmp_path):
         assert c2.tune_lookup("H1", 5, n_elem=64 * 1024) == 0                                 # too far
     finally:
         c2.close()
+        ctx.close()
 
 
 def test_batched_graph_replays(ctx, dpg):
