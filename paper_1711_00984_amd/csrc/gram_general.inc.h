@@ -89,6 +89,9 @@ constexpr int NTHREADS = 256;
 #ifndef DPG_REGF_MAX
 #define DPG_REGF_MAX 48
 #endif
+#ifndef DPG_REGF_MAX_HI
+#define DPG_REGF_MAX_HI 18   // FP64 with more than 8 points per direction (two-wave kernels)
+#endif
 #ifndef DPG_C2_MAX
 #define DPG_C2_MAX 24
 #endif
@@ -344,7 +347,8 @@ template <int S, int P, typename Real, int A, int B> struct S3Roles {
     return m;
   }();
   // field column fits in registers (not with line writes, whose staging needs the registers)
-  static constexpr bool REGF = ROUNDS == 1 && NFS * L <= DPG_REGF_MAX;
+  static constexpr bool REGF =
+      ROUNDS == 1 && NFS * L <= (L <= 8 || sizeof(Real) == 4 ? DPG_REGF_MAX : DPG_REGF_MAX_HI);
 };
 
 // Stage-2 table operands of a wave's fixed x-tile kept in registers: when a
@@ -870,10 +874,15 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
 }
 
 // Waves per SIMD the register allocation must allow: two when the LDS layout
-// leaves room for two workgroups per CU and the order is low enough for the
-// register state to fit without spilling, else one.
+// leaves room for two workgroups per CU and the register state fits without
+// spilling: up to 8 points per direction, and in FP64 for H1 and H(curl) up to
+// 10 points with the stage-3 fields kept in LDS (measured: H1 p = 9 13 % and
+// H(curl) p = 8, 9 3 % faster than with one wave; L2 slower, H(div) unchanged,
+// H(curl) p = 10 spills), else one.
 template <int S, int P, typename Real> constexpr int min_waves() {
-  return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && npoints(S, P) <= DPG_MINW2_LMAX) ? 2 : 1;
+  constexpr int L = npoints(S, P);
+  constexpr bool hi = sizeof(Real) == 8 && (S == SP_H1 || S == SP_HCURL) && L <= 10;
+  return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && (L <= DPG_MINW2_LMAX || hi)) ? 2 : 1;
 }
 
 template <int S, int P, typename Real, bool LISTED>
