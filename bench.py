@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_general_h1_p7_4096.json")
-KERNEL_SOURCES = ["gram_general.inc.h", "metric.h", "terms.h", "kernels.h", "gram_general_h1.hip"]
+KERNEL_SOURCES = ["gram_general.inc.h", "metric.h", "terms.h", "kernels.h", "launch_limits.h", "gram_general_h1.hip"]
 
 
 def log(*a):
