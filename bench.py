@@ -217,6 +217,7 @@ def main():
     torch.cuda.empty_cache()
     if a.extra:
         extra["batched_mixed_50000"] = run_mixed_full(ctx, dpg, stream)
+        extra["orders_p4_p8"] = run_orders(ctx, dpg, stream)
         extra["scaling"] = run_scaling(ctx, dpg, stream)
         extra["latency"] = run_latency(ctx, dpg, stream)
     serving = None
@@ -506,6 +507,40 @@ def run_latency(ctx, dpg, stream, reps=200):
     out["paper_hardware"] = "not stated in the paper"
     log(f"[bench] identity element rows: {rows}")
     return out
+
+
+def run_orders(ctx, dpg, stream, out_bytes=2 << 30):
+    """The metric's per-order figures: every space at p = 4..8 on the general
+    (quadrature) path, FP64, perturbed hexes (seed 7), about out_bytes of output per
+    launch (at most 8192 elements), the shipped tuning table's schedules.  Each row:
+    elements/s and the fraction of its roofline 1 / max(F / 78.6 TFLOP/s,
+    B / 8 TB/s) per element, F = the staged contraction's algorithmic flops, B = the
+    packed output + 192 B of trilinear geometry."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    rows = []
+    for space in ("H1", "HCURL", "HDIV", "L2"):
+        for p in range(4, 9):
+            m = dpg.packed_len(space, p)
+            n = int(max(16, min(8192, out_bytes // (m * 8))))
+            g = torch.from_numpy(meshgen.perturbed_hexes(n, seed=7)).cuda()
+            o = torch.empty(n * m, dtype=torch.float64, device="cuda")
+            w, per = time_launches(lambda: ctx.gram(space, p, g, out=o, stream=stream), 5, 3, stream)
+            ms = float(np.mean(per))
+            F = dpg.general_flops(space, p)
+            B = m * 8 + 192
+            t_roof = max(F / (PEAK_FP64_TFLOPS * 1e12), B / (PEAK_HBM_GBS * 1e9))
+            eps = n / (ms * 1e-3)
+            rows.append({"space": space, "p": p, "n_elem": n, "kernel_ms": round(ms, 4), "elements_per_s": round(eps, 1),
+                         "roofline_elements_per_s": round(1 / t_roof, 1), "frac": round(eps * t_roof, 4),
+                         "bound": "mfma" if F / (PEAK_FP64_TFLOPS * 1e12) > B / (PEAK_HBM_GBS * 1e9) else "hbm",
+                         "tflops": round(F * eps / 1e12, 2), "hbm_gbs": round(B * eps / 1e9, 1)})
+            del o, g
+        torch.cuda.empty_cache()
+    log(f"[bench] per-order fractions: {[(r['space'], r['p'], r['frac']) for r in rows]}")
+    return rows
 
 
 def run_scaling(ctx, dpg, stream, out_bytes=2 << 30):
