@@ -6,18 +6,26 @@
 // factor overwrites them in place: G = U^T U, U upper triangular with a
 // positive diagonal (LAPACK's packed 'U' convention).
 //
-// One workgroup of four waves per element (per element and 16 right-hand sides
-// for the solve, 64 when n <= 256).  Both kernels walk 16-row blocks of a triangular solve with
-// U^T: a block first loses the product of the rows already finished (a
-// 16 x 16 x K contraction over packed columns on FP64 or FP32 MFMA), then 16 lanes
-// finish it against the block's 16 x 16 diagonal block of U.  The factorization is
-// that walk with the Gram's own columns as right-hand sides, one 64-column panel at
-// a time (the up-looking order: column j of U solves U[:j, :j]^T u = G[:j, j]),
-// each wave owning a 16-column tile of the panel; inside the panel's diagonal block
-// the wave holding the diagonal tile factors it (unblocked Cholesky in registers)
-// before the waves to its right substitute with it.  The solve splits each block's
-// contraction over the four waves (4-wide k steps dealt round robin, summed through
-// LDS), or for small Grams gives each wave its own 16 right-hand sides.
+// Both kernels go down the matrix in block rows of 64 (four 16-row sub-blocks).
+// A wave owns a 64 x 16 tile of the block row (four MFMA accumulators) and first
+// removes from it, in one contraction on FP64 or FP32 MFMA, everything the rows
+// above contribute; that contraction is almost all of the arithmetic.  Its k
+// steps are dealt so that each lane reads four consecutive entries of a packed
+// column (whole 128-byte runs per 16 lanes), and the four sub-blocks share the
+// right-hand operand.  What is left is the 64 x 64 diagonal block: its four
+// sub-blocks are finished in order, each by MFMA products with the sub-blocks
+// already finished and a 16 x 16 triangular substitution done in the
+// accumulator layout itself (one column per 16-lane row group, unknowns
+// broadcast by shuffles), with the block's factor staged in LDS.
+//
+// Factorization (k_potrf, one workgroup of four waves per element): for block row
+// R, U[R, :] = U[R, R]^{-T} (G[R, :] - U[:R, R]^T U[:R, :]).  The four tiles of the
+// diagonal block go first, one per wave, in step with barriers (the wave on the
+// diagonal factors its 16 x 16 tile, the waves to its right substitute with it);
+// the tiles right of the diagonal block then need nothing more from other waves
+// and go round robin.  Solve (k_potrs, one workgroup per element and 64
+// right-hand sides, 16 per wave): U^T y = b down the block rows, then U x = y up
+// them, the diagonal block of each block row staged in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,177 +40,299 @@ typedef double c4d __attribute__((ext_vector_type(4)));
 typedef float c4f __attribute__((ext_vector_type(4)));
 
 // v_mfma_*_16x16x4: lane i + 16 k holds A[i][k] and B[k][i]; accumulator
-// register r of lane (g = lane / 16, j = lane % 16) holds C[row(g, r)][j].
+// register r of lane (g = lane / 16, j = lane % 16) holds C[row(g, r)][j], so
+// row k sits in lane group grp(k), register reg(k).
 template <typename Real> struct Mfma;
 template <> struct Mfma<double> {
   typedef c4d acc;
   static __device__ __forceinline__ acc mac(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+  static constexpr int row(int g, int r) { return g + 4 * r; }
+  static constexpr int grp(int k) { return k & 3; }
+  static constexpr int reg(int k) { return k >> 2; }
 };
 template <> struct Mfma<float> {
   typedef c4f acc;
   static __device__ __forceinline__ acc mac(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+  static constexpr int row(int g, int r) { return 4 * g + r; }
+  static constexpr int grp(int k) { return k >> 2; }
+  static constexpr int reg(int k) { return k & 3; }
 };
 
-constexpr int NB = 16;            // block rows / panel columns
-constexpr int NT = 256;
+constexpr int NB = 16;            // MFMA tile, sub-block rows
+constexpr int NS = 4;             // sub-blocks per block row
+constexpr int BR = NB * NS;       // block row
+constexpr int LDB = NB + 1;       // leading dimension of a staged 16 x 16 block of U
+constexpr int NBLK = NS * (NS + 1) / 2;           // blocks on or above the diagonal of a diagonal block
+constexpr int KC = 16;            // k per staged chunk of the left operand
+constexpr int CH = NS * KC * NB;  // entries per staged chunk (64 rows x 16 k)
+constexpr int NT = 256;                          // four waves; four workgroups per CU (<= 128 registers)
 constexpr int NW = NT / 64;
 constexpr int64_t kMaxGrid = int64_t(1) << 22;   // workgroups per launch
-
-// This wave's share of C[i][j] = sum_{k0 <= k < k1} A(i, k) B(k, j), 0 <= i, j < 16:
-// 4-wide k steps go round robin to NWV waves (wv: this wave's place among them).
-// a(i, k) and b(k, j) are only called for k0 <= k < k1 and return zero outside the
-// matrices.  Full waves only.
-template <typename Real, int NWV = NW, typename FA, typename FB>
-__device__ __forceinline__ typename Mfma<Real>::acc wave_gemm(FA a, FB b, int64_t k0, int64_t k1, int wv, int lane) {
-  typedef Mfma<Real> M;
-  typename M::acc c = {0, 0, 0, 0};
-  const int i = lane & 15, kk = lane >> 4;
-  constexpr int64_t step = 4 * NWV;
-  int64_t kb = k0 + 4 * wv;
-  for (; kb + 3 * step < k1; kb += 4 * step) {   // four steps, loads first
-    Real av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t k = kb + u * step + kk;
-      const bool ok = k < k1;
-      av[u] = ok ? a(i, k) : Real(0);
-      bv[u] = ok ? b(k, i) : Real(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) c = M::mac(av[u], bv[u], c);
-  }
-  for (; kb < k1; kb += step) {
-    const int64_t k = kb + kk;
-    const bool ok = k < k1;
-    c = M::mac(ok ? a(i, k) : Real(0), ok ? b(k, i) : Real(0), c);
-  }
-  return c;
-}
-
-template <typename Real>
-__device__ __forceinline__ void spill(const typename Mfma<Real>::acc& c, Real* red, int lane) {
-  const int g = lane >> 4, j = lane & 15;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) red[Mfma<Real>::row(g, r) * NB + j] = c[r];
-}
 
 // Packed 'U' column pointer.
 __device__ __forceinline__ int64_t colp(int64_t j) { return j * (j + 1) / 2; }
 
-// Substitution with a 16 x 16 triangular block, one right-hand side per lane.
-// The unknowns still to be found sit in registers in the order they are
-// reached: each step takes v[0], removes it from the rest and shifts them down
-// one register, so every register index is static while the step k stays a
-// loop counter (a fully unrolled substitution would hold all 136 block entries
-// in registers).  t(k, m) is the coefficient linking the unknown of step k to
-// the one m steps later, rpiv(k) the reciprocal of the pivot t(k, 0) (computed once
-// per block, so a step costs one multiply); put(k, x) receives the unknown of step k.
-template <typename Real, typename FT, typename FR, typename FP>
-__device__ __forceinline__ void substitute(Real (&v)[NB], FT t, FR rpiv, FP put) {
-#pragma unroll 1
-  for (int k = 0; k < NB; ++k) {
-    const Real x = v[0] * rpiv(k);
-    put(k, x);
-#pragma unroll
-    for (int m = 1; m < NB; ++m) v[m - 1] = v[m] - t(k, m) * x;
-  }
-}
+// Block (t, s), t <= s, of a 64 x 64 diagonal block staged in LDS: row-major 16 x 16
+// with leading dimension LDB, the ten blocks one after the other.
+__device__ __forceinline__ int blk_off(int t, int s) { return (t * NS + s - t * (t + 1) / 2) * NB * LDB; }
 
-// One wave's 16 x 16 x K contraction over contiguous columns, all k steps its own:
-// lane (i, kk) holds column i of A at pa and column i of B at pb (va, vb false: zero).
-template <typename Real>
-__device__ __forceinline__ typename Mfma<Real>::acc wave_gemm_own(const Real* pa, const Real* pb, bool va, bool vb,
-                                                                  int64_t k1, int lane) {
+// The left operand of the contractions, 64 rows by KC k, is staged in LDS once per
+// workgroup and chunk, in the order the MFMAs take it: the entry for row 16 s + i and
+// k = 4 kk + q (of the chunk) sits at (s * 4 + q) * 64 + 16 kk + i, so lane 16 kk + i
+// of any wave reads its step-q operand of sub-block s at (s * 4 + q) * 64 + lane.
+__device__ __forceinline__ int stage_idx(int s, int q, int kk, int i) { return (s * 4 + q) * 64 + kk * 16 + i; }
+
+// Contraction over nch chunks of KC k, four waves in step: c[s] += sum_k A_s(i, k) B(k, j)
+// for the four sub-blocks s, on the waves with act (the waves run in step, so a wave that
+// needs fewer sub-blocks would only wait at the barrier; it computes them all).  load_a(ch, v) fetches this
+// thread's four entries of the left operand's chunk ch and put_a(buf, v) stores them
+// in the staging order; load_b(ch, v) fetches this lane's four right-hand entries
+// (k = 16 ch + 4 kk + q in step q).  The next chunk's global loads are in flight while
+// the MFMAs of the current one run; one barrier per chunk.  Every wave of the
+// workgroup calls it with the same nch.
+template <typename Real, typename FLA, typename FPA, typename FLB>
+__device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act, FLA load_a, FPA put_a,
+                                                FLB load_b, typename Mfma<Real>::acc (&c)[NS], int lane) {
   typedef Mfma<Real> M;
-  typename M::acc c = {0, 0, 0, 0};
-  const int kk = lane >> 4;
-  int64_t kb = 0;
-  for (; kb + 16 <= k1; kb += 16) {                // four steps, loads first
-    Real av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      av[u] = va ? pa[kb + 4 * u + kk] : Real(0);
-      bv[u] = vb ? pb[kb + 4 * u + kk] : Real(0);
+  if (nch <= 0) return;
+  Real va[4], vb[4], nb[4];
+  load_a(0, va);
+  if (act) load_b(0, vb);
+  put_a(sA, va);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const Real* cur = sA + (ch & 1) * CH;
+    const bool more = ch + 1 < nch;
+    if (more) {
+      load_a(ch + 1, va);
+      if (act) load_b(ch + 1, nb);
     }
+    if (act) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) c = M::mac(av[u], bv[u], c);
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) c[s] = M::mac(cur[(s * 4 + q) * 64 + lane], vb[q], c[s]);
+    }
+    if (more) {
+      put_a(sA + ((ch + 1) & 1) * CH, va);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vb[q] = nb[q];
+    }
+    __syncthreads();
   }
-  for (; kb < k1; kb += 4) {
-    const int64_t k = kb + kk;
-    const bool ok = k < k1;
-    c = M::mac(ok && va ? pa[k] : Real(0), ok && vb ? pb[k] : Real(0), c);
-  }
-  return c;
 }
 
-// Panels of PW = 64 columns, one 16-column tile per wave.  For each 16-row block ib
-// down the panel, every wave whose tile lies on or right of the diagonal contracts
-// its own tile (no cross-wave sum): S = G[Ib, tile] - U[:ib, Ib]^T U[:ib, tile], with
-// the Gram entries fetched beforehand into the accumulator's own layout.  Above the
-// panel's diagonal block the tile is finished by substitution with U[Ib, Ib] (read
-// from memory); inside it, the wave holding the diagonal tile factors it first and the
-// waves to its right substitute with the new factor.  n / 16 (n / 64 + 1) / 2 row
-// blocks per element instead of n^2 / 512 with 16-column panels.
+// v -= T^T x for a staged 16 x 16 block T and x in the accumulator layout, whose
+// register q holds the k of MFMA step q: x is the right operand as it stands.
 template <typename Real>
-__global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, int64_t n_elem,
-                                              int32_t* __restrict__ info) {
+__device__ __forceinline__ void sub_tn(typename Mfma<Real>::acc& v, const Real* T, const typename Mfma<Real>::acc& x,
+                                       int lane) {
   typedef Mfma<Real> M;
-  constexpr int PW = NB * NW;
-  __shared__ Real s_S[NW][NB][NB + 1];      // each wave's tile, row-major
-  __shared__ Real s_T[NB][2 * NB];          // U[ib + r][ib + c] at [r][c]; columns >= NB zero
-  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r]
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v = M::mac(-T[M::row(g, q) * LDB + i], x[q], v);
+}
+
+// v -= T x (T as above).
+template <typename Real>
+__device__ __forceinline__ void sub_nn(typename Mfma<Real>::acc& v, const Real* T, const typename Mfma<Real>::acc& x,
+                                       int lane) {
+  typedef Mfma<Real> M;
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v = M::mac(-T[i * LDB + M::row(g, q)], x[q], v);
+}
+
+// T^T x = v in place for the staged upper triangular block T (rd[k] = 1 / T[k][k]), v in
+// the accumulator layout (the 16 right-hand sides are the columns j = lane % 16).  Step
+// k finishes unknown k with its reciprocal pivot, broadcasts it along its column and
+// removes it from the rows below.  Unknowns from row h on (past the matrix) are set to
+// zero so that they reach no valid row.
+template <typename Real>
+__device__ __forceinline__ void subst_fwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int h,
+                                          int lane) {
+  typedef Mfma<Real> M;
+  const int g = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int gk = M::grp(k), rk = M::reg(k);
+    Real x = __shfl(v[rk] * rd[k], gk * 16 + j);
+    if (k >= h) x = Real(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = M::row(g, r);
+      v[r] -= (m > k ? T[k * LDB + m] : Real(0)) * x;
+    }
+    if (g == gk) v[rk] = x;
+    __builtin_amdgcn_sched_barrier(0);   // keep the steps' coefficient loads from piling up in registers
+  }
+}
+
+// T x = v in place (T, rd, h as above), bottom up.
+template <typename Real>
+__device__ __forceinline__ void subst_bwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int h,
+                                          int lane) {
+  typedef Mfma<Real> M;
+  const int g = lane >> 4, j = lane & 15;
+#pragma unroll
+  for (int k = NB - 1; k >= 0; --k) {
+    const int gk = M::grp(k), rk = M::reg(k);
+    Real x = __shfl(v[rk] * rd[k], gk * 16 + j);
+    if (k >= h) x = Real(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = M::row(g, r);
+      v[r] -= (m < k ? T[m * LDB + k] : Real(0)) * x;
+    }
+    if (g == gk) v[rk] = x;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Left operand "columns of U": chunk ch of U[k][r0 + r], k = 16 ch + .., r < 64 (columns
+// past n clamped to the last; rows past the matrix only reach output rows that are never
+// stored).  Thread t takes column r0 + t / 4, four consecutive k.
+template <typename Real>
+struct ColsOperand {
+  const Real* col;
+  int kq, s, i, kk;
+  __device__ ColsOperand(const Real* u, int64_t n, int64_t r0, int tid) {
+    const int r = tid >> 2;
+    kq = 4 * (tid & 3);
+    col = u + colp(std::min<int64_t>(r0 + r, n - 1));
+    s = r >> 4;
+    i = r & 15;
+    kk = tid & 3;
+  }
+  __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = col[KC * ch + kq + q];
+  }
+  __device__ __forceinline__ void put(Real* buf, const Real (&v)[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) buf[stage_idx(s, q, kk, i)] = v[q];
+  }
+};
+
+// Left operand "rows of U": chunk ch of U[r0 + r][k], k = k0 + 16 ch + .. (zero from kend
+// on), r < 64.  Thread t takes column k0 + 16 ch + t / 16, four consecutive rows.
+template <typename Real>
+struct RowsOperand {
+  const Real* u;
+  int64_t r0, k0, kend;
+  int kc, rq;
+  __device__ RowsOperand(const Real* u_, int64_t r0_, int64_t k0_, int64_t kend_, int tid)
+      : u(u_), r0(r0_), k0(k0_), kend(kend_), kc(tid >> 4), rq(4 * (tid & 15)) {}
+  __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
+    const int64_t k = k0 + KC * ch + kc;
+    const bool ok = k < kend;
+    const Real* p = u + colp(ok ? k : kend - 1) + r0 + rq;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = ok ? p[m] : Real(0);
+  }
+  __device__ __forceinline__ void put(Real* buf, const Real (&v)[4]) const {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = rq + m;
+      buf[stage_idx(r >> 4, kc & 3, kc >> 2, r & 15)] = v[m];
+    }
+  }
+};
+
+// Right operand: this lane's column pb, k = k0 + 16 ch + 4 kk + q (zero from kend on).
+template <typename Real>
+__device__ __forceinline__ void load_rhs(const Real* pb, int64_t k0, int64_t kend, int64_t ch, int lane, Real (&v)[4]) {
+  const int64_t kb = k0 + KC * ch + 4 * (lane >> 4);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t k = kb + q;
+    v[q] = k < kend ? pb[k] : Real(0);
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t n, int64_t n_elem,
+                                                 int32_t* __restrict__ info) {
+  typedef Mfma<Real> M;
+  typedef typename M::acc acc;
+  __shared__ Real s_U[NBLK * NB * LDB];     // U on the diagonal block of the block row, blocks (t <= s)
+  __shared__ Real s_A[2 * CH];              // staged left operand (two chunks); the diagonal tile being
+                                            // factored borrows the first
+  __shared__ Real s_rd[BR];                 // reciprocal pivots of the diagonal block
   __shared__ int s_fail;
   const int64_t e = blockIdx.x;
   if (e >= n_elem) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
   Real* a = ap + e * (n * (n + 1) / 2);
-  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
+  Real* s_S = s_A;
+  const acc zero = {0, 0, 0, 0};
 
-  for (int64_t jb = 0; jb < n; jb += PW) {
-    const int64_t c0 = jb + NB * wv;                         // this wave's first column
-    const int wc = int(std::max<int64_t>(0, std::min<int64_t>(NB, n - c0)));   // its columns (0: none)
-    const int64_t iend = std::min<int64_t>(jb + PW, n);
-    for (int64_t ib = 0; ib < iend; ib += NB) {
-      const bool inside = ib >= jb;                          // row block inside the panel's diagonal block
-      const int dw = inside ? int((ib - jb) / NB) : -1;      // wave holding the diagonal tile
-      const bool act = wc > 0 && c0 >= ib;
-      const bool dtile = act && c0 == ib;
-      // Gram entries of this lane's accumulator slots, and (above the diagonal block) one
-      // entry of U[Ib, Ib] per thread, fetched before the contraction
-      Real gv[4];
+  // S = G - S on this lane's accumulator slots (rows r0 + 16 s + .., column cb + lane % 16)
+  auto gram_minus = [&](int64_t r0, int s, int64_t cb, acc& S) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = M::row(lg, r);
-        const bool ok = act && li < wc && (!dtile || row <= li);
-        gv[r] = ok ? a[colp(c0 + li) + ib + row] : Real(0);
-      }
-      const int tr = tid & 15, tc = tid >> 4;
-      const Real tv = (!inside && tr <= tc) ? a[colp(ib + tc) + ib + tr] : Real(0);
-      typename M::acc c = {0, 0, 0, 0};
-      if (act) c = wave_gemm_own<Real>(a + colp(ib + li), a + colp(c0 + li), ib + li < n, li < wc, ib, lane);
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + NB * s + M::row(lg, r), col = cb + li;
+      const Real g = (row <= col && col < n) ? a[colp(col) + row] : Real(0);
+      S[r] = g - S[r];
+    }
+  };
+  auto store = [&](int64_t r0, int s, int64_t cb, const acc& S) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) s_S[wv][M::row(lg, r)][li] = gv[r] - c[r];
-      if (!inside) {
-        s_T[tr][tc] = tv;
-        if (tr == tc) s_rd[tr] = Real(1) / tv;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + NB * s + M::row(lg, r), col = cb + li;
+      if (row <= col && col < n) a[colp(col) + row] = S[r];
+    }
+  };
+  auto blk = [&](int t, int s) { return s_U + blk_off(t, s); };
+  // S = U[:r0, R]^T U[:r0, cb ..] (active waves)
+  auto contract = [&](int64_t r0, int64_t cb, bool act, acc (&S)[NS]) {
+    const ColsOperand<Real> A(a, n, r0, tid);
+    const Real* pb = a + colp(std::min<int64_t>(cb + li, n - 1));
+    contract_staged<Real>(
+        s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
+        [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+        [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(pb, 0, r0, ch, lane, v); }, S, lane);
+  };
+
+  for (int64_t r0 = 0; r0 < n; r0 += BR) {
+    const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));   // sub-blocks in this block row
+    // ---- the diagonal block, wave wv on columns r0 + 16 wv ..
+    {
+      const bool have = wv < nsb;
+      const int64_t cb = r0 + NB * wv;
+      acc S[NS] = {zero, zero, zero, zero};
+      contract(r0, cb, have, S);            // (the sub-blocks below the diagonal go unused)
+      if (have) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (s <= wv) gram_minus(r0, s, cb, S[s]);
       }
-      __syncthreads();
-      if (inside) {
-        if (dtile && lane < NB) {           // unblocked Cholesky of the diagonal tile, one column per lane
-          const int j = lane, w = wc;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s >= nsb) break;
+        const int h = int(std::min<int64_t>(NB, n - r0 - NB * s));
+        if (have && wv >= s) {
+#pragma unroll
+          for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
+          if (wv == s) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s_S[M::row(lg, r) * (NB + 1) + li] = S[s][r];
+          }
+        }
+        __syncthreads();
+        if (wv == s && lane < NB) {         // unblocked Cholesky of the diagonal tile, one column per lane
+          const int j = lane;
           Real cl[NB];
 #pragma unroll
-          for (int i = 0; i < NB; ++i) cl[i] = s_S[wv][i][j];
+          for (int i = 0; i < NB; ++i) cl[i] = s_S[i * (NB + 1) + j];
           int fail = 0;
 #pragma unroll
           for (int k = 0; k < NB; ++k) {
-            if (k < w && !fail) {           // uniform: w and the pivot are the same in every lane
+            if (k < h && !fail) {           // uniform: h and the pivot are the same in every lane
               const Real d = __shfl(cl[k], k);
               if (!(d > Real(0))) {
                 fail = k + 1;
@@ -214,15 +344,16 @@ __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, 
               }
             }
           }
-          if (j < w && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
+          const int64_t ib = r0 + NB * s;
+          if (j < h && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
             Real* dst = a + colp(ib + j) + ib;
 #pragma unroll
             for (int i = 0; i < NB; ++i)
               if (i <= j) dst[i] = cl[i];
           }
 #pragma unroll
-          for (int i = 0; i < NB; ++i) s_T[i][j] = i <= j ? cl[i] : Real(0);
-          s_rd[j] = j < w ? Real(1) / cl[j] : Real(1);
+          for (int i = 0; i < NB; ++i) blk(s, s)[i * LDB + j] = i <= j ? cl[i] : Real(0);
+          s_rd[NB * s + j] = j < h ? Real(1) / cl[j] : Real(1);
           if (j == 0) s_fail = fail ? int(ib) + fail : 0;
         }
         __syncthreads();
@@ -230,212 +361,157 @@ __global__ void __launch_bounds__(NT) k_potrf(Real* __restrict__ ap, int64_t n, 
           if (tid == 0 && info) info[e] = s_fail;
           return;
         }
-      }
-      if (act && !dtile && lane < NB) {     // U[Ib, Ib]^T x = s, one column of the tile per lane
-        const int j = lane;
-        Real v[NB];
+        if (have && wv > s) {               // U[s, s]^T x = S[s]: this tile's rows of sub-block s
+          subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, h, lane);
+          store(r0, s, cb, S[s]);
 #pragma unroll
-        for (int r = 0; r < NB; ++r) v[r] = s_S[wv][r][j];
-        Real* dst = a + colp(c0 + j) + ib;
-        substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
-                         [&](int k, Real x) {
-                           if (j < wc) dst[k] = x;
-                         });
+          for (int r = 0; r < 4; ++r) blk(s, wv)[M::row(lg, r) * LDB + li] = S[s][r];
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    // ---- the tiles right of the diagonal block, four at a time (one per wave)
+    for (int64_t cg = r0 + BR; cg < n; cg += BR) {
+      const int64_t cb = cg + NB * wv;
+      const bool act = cb < n;
+      acc S[NS] = {zero, zero, zero, zero};
+      contract(r0, cb, act, S);
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (s >= nsb) break;
+          gram_minus(r0, s, cb, S[s]);
+#pragma unroll
+          for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
+          subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+          store(r0, s, cb, S[s]);
+        }
+      }
+    }
+    __syncthreads();                        // block row finished before the next one reads it
   }
   if (tid == 0 && info) info[e] = 0;
 }
 
-template <typename Real>
-__global__ void __launch_bounds__(NT) k_potrs(const Real* __restrict__ up, int64_t n, int64_t n_elem, int64_t nrhs,
-                                              int64_t e0, Real* __restrict__ b) {
-  __shared__ Real s_red[NW][NB * NB];
-  __shared__ Real s_S[NB][NB + 1];
-  __shared__ Real s_T[NB][2 * NB];          // forward: U[ib + r][ib + c] at [r][c]; backward: at [c][NB - 1 - r]
-  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r] (rows past n: 1)
-  const int64_t nblk = (nrhs + NB - 1) / NB;
-  const int64_t e = e0 + int64_t(blockIdx.x) / nblk, cb = int64_t(blockIdx.x) % nblk;
-  if (e >= n_elem) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const Real* u = up + e * (n * (n + 1) / 2);
-  Real* x = b + e * n * nrhs + cb * NB * n;        // column j of this block at x + j n
-  const int wc = int(std::min<int64_t>(NB, nrhs - cb * NB));
-  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
-
-  // The 16 x 16 diagonal block U[ib + r][ib + c] (rows and columns past n the identity).
-  auto fetch_t = [&](int64_t ib, int h) {
-    const int r = tid & 15, c = tid >> 4;
-    return (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
-  };
-  auto put_t = [&](Real t, bool fwd) {
-    const int r = tid & 15, c = tid >> 4;
-    if (fwd)
-      s_T[r][c] = t;
-    else
-      s_T[c][NB - 1 - r] = t;
-    if (r == c) s_rd[r] = Real(1) / t;
-  };
-  auto fetch_x = [&](int64_t ib, int h) {
-    const int i = tid >> 4, j = tid & 15;
-    return (i < h && j < wc) ? x[j * n + ib + i] : Real(0);
-  };
-  auto combine = [&](Real s) {
-    const int i = tid >> 4, j = tid & 15;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) s -= s_red[q][i * NB + j];
-    s_S[i][j] = s;
-  };
-
-  // U^T y = b, top down.
-  for (int64_t ib = 0; ib < n; ib += NB) {
-    const int h = int(std::min<int64_t>(NB, n - ib));
-    const Real tv = fetch_t(ib, h), xv = fetch_x(ib, h);
-    const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(ib + i) + k] : Real(0); },
-                                   [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
-                                   0, ib, wv, lane);
-    spill<Real>(c, s_red[wv], lane);
-    put_t(tv, true);
-    __syncthreads();
-    combine(xv);
-    __syncthreads();
-    if (tid < NB) {                         // U[Ib, Ib]^T y = s, rows top down
-      const int j = tid;
-      Real v[NB];
-#pragma unroll
-      for (int r = 0; r < NB; ++r) v[r] = s_S[r][j];
-      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
-                       [&](int k, Real y) {
-                         if (j < wc && k < h) x[j * n + ib + k] = y;
-                       });
-    }
-    __syncthreads();
-  }
-  // U x = y, bottom up.
-  for (int64_t ib = ((n - 1) / NB) * NB; ib >= 0; ib -= NB) {
-    const int h = int(std::min<int64_t>(NB, n - ib));
-    const Real tv = fetch_t(ib, h), xv = fetch_x(ib, h);
-    const auto c = wave_gemm<Real>([&](int i, int64_t k) { return i < h ? u[colp(k) + ib + i] : Real(0); },
-                                   [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); },
-                                   ib + h, n, wv, lane);
-    spill<Real>(c, s_red[wv], lane);
-    put_t(tv, false);
-    __syncthreads();
-    combine(xv);
-    __syncthreads();
-    if (tid < NB) {                         // U[Ib, Ib] x = s, step k is row NB - 1 - k
-      const int j = tid;
-      Real v[NB];
-#pragma unroll
-      for (int r = 0; r < NB; ++r) v[r] = s_S[NB - 1 - r][j];
-      // U[NB-1-k-m][NB-1-k] sits at s_T[NB-1-k][k+m]
-      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; },
-                       [&](int k) { return s_rd[NB - 1 - k]; }, [&](int k, Real y) {
-                         const int r = NB - 1 - k;
-                         if (j < wc && r < h) x[j * n + ib + r] = y;
-                       });
-    }
-    __syncthreads();
-  }
+// Workgroup b of g runs on XCD b % 8 (the dispatcher deals workgroups round robin); the
+// logical workgroup is numbered so that each XCD takes one contiguous range, keeping the
+// workgroups of one element (the same factor U) on one XCD and its L2.
+__device__ __forceinline__ int64_t xcd_major(int64_t b, int64_t g) {
+  const int64_t x = b & 7, per = g >> 3, rem = g & 7;
+  return x * per + std::min<int64_t>(x, rem) + (b >> 3);
 }
 
-// The solve for small Grams (n <= 256, where the round-robin contraction is short and
-// the workgroups many): each wave owns 16 right-hand sides (64 per workgroup) and
-// contracts its own tile over all k, so U is read once per 64 right-hand sides and
-// there is no cross-wave sum; the 16 x 16 diagonal block of U is fetched once per
-// row block for the four waves.
 template <typename Real>
-__global__ void __launch_bounds__(NT) k_potrs_w(const Real* __restrict__ up, int64_t n, int64_t n_elem, int64_t nrhs,
-                                                int64_t e0, Real* __restrict__ b) {
+__global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, int64_t n, int64_t n_elem, int64_t nrhs,
+                                                 int64_t e0, Real* __restrict__ b) {
   typedef Mfma<Real> M;
-  constexpr int CW = NB * NW;               // right-hand sides per workgroup
-  __shared__ Real s_S[NW][NB][NB + 1];      // each wave's tile, row-major
-  __shared__ Real s_T[NB][2 * NB];          // forward: U[ib + r][ib + c] at [r][c]; backward: at [c][NB - 1 - r]
-  __shared__ Real s_rd[NB];                 // 1 / U[ib + r][ib + r] (rows past n: 1)
-  const int64_t nblk = (nrhs + CW - 1) / CW;
-  const int64_t e = e0 + int64_t(blockIdx.x) / nblk, cb = int64_t(blockIdx.x) % nblk;
+  typedef typename M::acc acc;
+  __shared__ Real s_U[NBLK * NB * LDB];     // the block row's diagonal block of U, blocks (t <= s)
+  __shared__ Real s_A[2 * CH];              // staged left operand
+  __shared__ Real s_rd[BR];                 // reciprocal pivots (rows past n: 1)
+  const int64_t nblk = (nrhs + BR - 1) / BR;
+  const int64_t wg = xcd_major(blockIdx.x, gridDim.x);
+  const int64_t e = e0 + wg / nblk, cbk = wg % nblk;
   if (e >= n_elem) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
   const Real* u = up + e * (n * (n + 1) / 2);
-  const int64_t c0 = cb * CW + NB * wv;     // this wave's first right-hand side
-  const int wc = int(std::max<int64_t>(0, std::min<int64_t>(NB, nrhs - c0)));
-  Real* x = b + e * n * nrhs + c0 * n;      // its column j at x + j n (not read when wc = 0)
-  s_T[tid >> 4][NB + (tid & 15)] = Real(0);
+  const int64_t c0 = cbk * BR + NB * wv;    // this wave's first right-hand side
+  const bool act = c0 < nrhs;
+  const bool colok = c0 + li < nrhs;
+  Real* xc = b + e * n * nrhs + std::min<int64_t>(c0 + li, nrhs - 1) * n;   // this lane's right-hand side
+  const acc zero = {0, 0, 0, 0};
+  auto blk = [&](int t, int s) { return s_U + blk_off(t, s); };
 
-  auto fetch_t = [&](int64_t ib, int h) {
-    const int r = tid & 15, c = tid >> 4;
-    return (r <= c && c < h) ? u[colp(ib + c) + ib + r] : Real(r == c ? 1 : 0);
+  // the blocks (t <= s) of U on rows and columns r0 .. r0 + 63 (the identity past n)
+  auto stage = [&](int64_t r0) {
+    for (int idx = tid; idx < NBLK * NB * NB; idx += NT) {
+      const int bi = idx / (NB * NB), w = idx % (NB * NB), r = w % NB, c = w / NB;
+      int t = 0, s = bi;
+      while (s >= NS - t) { s -= NS - t; ++t; }
+      s += t;                               // block bi is (t, s)
+      const int64_t gr = r0 + NB * t + r, gc = r0 + NB * s + c;
+      Real v = (t == s && r == c) ? Real(1) : Real(0);
+      if (gr <= gc && gc < n) v = u[colp(gc) + gr];
+      blk(t, s)[r * LDB + c] = v;
+      if (t == s && r == c) s_rd[NB * t + r] = Real(1) / v;
+    }
   };
-  auto put_t = [&](Real t, bool fwd) {
-    const int r = tid & 15, c = tid >> 4;
-    if (fwd)
-      s_T[r][c] = t;
-    else
-      s_T[c][NB - 1 - r] = t;
-    if (r == c) s_rd[r] = Real(1) / t;
-  };
-  // right-hand side entries of this lane's accumulator slots
-  auto fetch_x = [&](int64_t ib, int h, Real (&xv)[4]) {
+  auto rhs_minus = [&](int64_t r0, int s, acc& S) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = M::row(lg, r);
-      xv[r] = (row < h && li < wc) ? x[li * n + ib + row] : Real(0);
+      const int64_t row = r0 + NB * s + M::row(lg, r);
+      S[r] = ((colok && row < n) ? xc[row] : Real(0)) - S[r];
     }
   };
-  auto put_s = [&](const Real (&xv)[4], const typename M::acc& c) {
+  auto store = [&](int64_t r0, int s, const acc& S) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) s_S[wv][M::row(lg, r)][li] = xv[r] - c[r];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + NB * s + M::row(lg, r);
+      if (colok && row < n) xc[row] = S[r];
+    }
   };
 
-  // U^T y = b, top down.
-  for (int64_t ib = 0; ib < n; ib += NB) {
-    const int h = int(std::min<int64_t>(NB, n - ib));
-    const Real tv = fetch_t(ib, h);
-    Real xv[4];
-    fetch_x(ib, h, xv);
-    typename M::acc c = {0, 0, 0, 0};
-    if (wc > 0) c = wave_gemm_own<Real>(u + colp(ib + li), x + li * n, li < h, li < wc, ib, lane);
-    put_s(xv, c);
-    put_t(tv, true);
-    __syncthreads();
-    if (wc > 0 && lane < NB) {              // U[Ib, Ib]^T y = s, rows top down
-      const int j = lane;
-      Real v[NB];
+  // U^T y = b, top down
+  for (int64_t r0 = 0; r0 < n; r0 += BR) {
+    const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));
+    __syncthreads();                        // the previous block row is done with s_U
+    stage(r0);
+    acc S[NS] = {zero, zero, zero, zero};
+    {
+      const ColsOperand<Real> A(u, n, r0, tid);
+      contract_staged<Real>(
+          s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
+          [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+          [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, 0, r0, ch, lane, v); }, S, lane);
+    }
+    if (act) {
 #pragma unroll
-      for (int r = 0; r < NB; ++r) v[r] = s_S[wv][r][j];
-      substitute<Real>(v, [&](int k, int m) { return s_T[k][k + m]; }, [&](int k) { return s_rd[k]; },
-                       [&](int k, Real y) {
-                         if (j < wc && k < h) x[j * n + ib + k] = y;
-                       });
+      for (int s = 0; s < NS; ++s)
+        if (s < nsb) rhs_minus(r0, s, S[s]);
     }
     __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s >= nsb) break;
+#pragma unroll
+        for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
+        subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+        store(r0, s, S[s]);
+      }
+    }
   }
-  // U x = y, bottom up.
-  for (int64_t ib = ((n - 1) / NB) * NB; ib >= 0; ib -= NB) {
-    const int h = int(std::min<int64_t>(NB, n - ib));
-    const Real tv = fetch_t(ib, h);
-    Real xv[4];
-    fetch_x(ib, h, xv);
-    typename M::acc c = {0, 0, 0, 0};
-    if (wc > 0)
-      c = wave_gemm<Real, 1>([&](int i, int64_t k) { return i < h ? u[colp(k) + ib + i] : Real(0); },
-                             [&](int64_t k, int j) { return j < wc ? x[j * n + k] : Real(0); }, ib + h, n, 0, lane);
-    put_s(xv, c);
-    put_t(tv, false);
+  // U x = y, bottom up
+  for (int64_t r0 = ((n - 1) / BR) * BR; r0 >= 0; r0 -= BR) {
+    const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));
     __syncthreads();
-    if (wc > 0 && lane < NB) {              // U[Ib, Ib] x = s, step k is row NB - 1 - k
-      const int j = lane;
-      Real v[NB];
+    stage(r0);
+    acc S[NS] = {zero, zero, zero, zero};
+    {
+      const int64_t k0 = r0 + BR;
+      const RowsOperand<Real> A(u, r0, k0, n, tid);
+      contract_staged<Real>(
+          s_A, k0 < n ? (n - k0 + KC - 1) / KC : 0, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
+          [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+          [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, k0, n, ch, lane, v); }, S, lane);
+    }
+    if (act) {
 #pragma unroll
-      for (int r = 0; r < NB; ++r) v[r] = s_S[wv][NB - 1 - r][j];
-      substitute<Real>(v, [&](int k, int m) { return s_T[NB - 1 - k][k + m]; },
-                       [&](int k) { return s_rd[NB - 1 - k]; }, [&](int k, Real y) {
-                         const int r = NB - 1 - k;
-                         if (j < wc && r < h) x[j * n + ib + r] = y;
-                       });
+      for (int s = 0; s < NS; ++s)
+        if (s < nsb) rhs_minus(r0, s, S[s]);
     }
     __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int s = NS - 1; s >= 0; --s) {
+        if (s >= nsb) continue;
+#pragma unroll
+        for (int t = s + 1; t < NS; ++t)
+          if (t < nsb) sub_nn<Real>(S[s], blk(s, t), S[t], lane);
+        subst_bwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+        store(r0, s, S[s]);
+      }
+    }
   }
 }
 
@@ -457,28 +533,17 @@ hipError_t launch_potrf(int prec, void* ap, int64_t n, int64_t n_elem, int32_t* 
 }
 
 hipError_t launch_potrs(int prec, const void* up, int64_t n, int64_t n_elem, int64_t nrhs, void* b, hipStream_t st) {
-  const bool wide = n <= 256;               // one tile per wave (64 right-hand sides per workgroup)
-  const int64_t cw = wide ? NB * NW : NB;
-  const int64_t nblk = (nrhs + cw - 1) / cw;
+  const int64_t nblk = (nrhs + BR - 1) / BR;
   const int64_t per = std::max<int64_t>(1, kMaxGrid / nblk);     // elements per launch
   for (int64_t e0 = 0; e0 < n_elem; e0 += per) {
     const int64_t ne = std::min(per, n_elem - e0);
     const unsigned grid = unsigned(ne * nblk);
-    if (prec) {
-      auto* u = static_cast<const float*>(up);
-      auto* x = static_cast<float*>(b);
-      if (wide)
-        hipLaunchKernelGGL(k_potrs_w<float>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
-      else
-        hipLaunchKernelGGL(k_potrs<float>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
-    } else {
-      auto* u = static_cast<const double*>(up);
-      auto* x = static_cast<double*>(b);
-      if (wide)
-        hipLaunchKernelGGL(k_potrs_w<double>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
-      else
-        hipLaunchKernelGGL(k_potrs<double>, dim3(grid), dim3(NT), 0, st, u, n, e0 + ne, nrhs, e0, x);
-    }
+    if (prec)
+      hipLaunchKernelGGL(k_potrs<float>, dim3(grid), dim3(NT), 0, st, static_cast<const float*>(up), n, e0 + ne,
+                         nrhs, e0, static_cast<float*>(b));
+    else
+      hipLaunchKernelGGL(k_potrs<double>, dim3(grid), dim3(NT), 0, st, static_cast<const double*>(up), n, e0 + ne,
+                         nrhs, e0, static_cast<double*>(b));
   }
   return hipGetLastError();
 }

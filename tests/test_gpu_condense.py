@@ -72,7 +72,7 @@ def check_factor(Up, G, prec, label):
     assert np.all(np.tril(U, -1) == 0)
 
 
-@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 33, 64, 100])
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 33, 64, 100, 129, 200, 257])
 def test_factor_synthetic(ctx, n):
     say("factor synthetic", n)
     rng = np.random.default_rng(400 + n)
@@ -104,11 +104,10 @@ def test_factor_element_grams(ctx, dpg, space, p):
         check_factor(U[e], og.unpack_upper(Gn[e], n), "fp64", f"{space} p={p} e={e}")
 
 
-@pytest.mark.parametrize("k", [1, 16, 17, 40])
-def test_failure_index(ctx, k):
+@pytest.mark.parametrize("n,k", [(48, 1), (48, 16), (48, 17), (48, 40), (130, 64), (130, 65), (130, 100)])
+def test_failure_index(ctx, n, k):
     """A pivot of exactly -1 at column k-1; the other elements are untouched by it."""
-    say("info", k)
-    n = 48
+    say("info", n, k)
     rng = np.random.default_rng(420 + k)
     Gs = np.stack([spd(n, rng) for _ in range(3)])
     R, _ = condense.cholesky_upper(Gs[1])
