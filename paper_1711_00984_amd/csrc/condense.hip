@@ -12,11 +12,14 @@
 // above contribute; that contraction is almost all of the arithmetic.  Its k
 // steps are dealt so that each lane reads four consecutive entries of a packed
 // column (whole 128-byte runs per 16 lanes), and the four sub-blocks share the
-// right-hand operand.  What is left is the 64 x 64 diagonal block: its four
-// sub-blocks are finished in order, each by MFMA products with the sub-blocks
-// already finished and a 16 x 16 triangular substitution done in the
-// accumulator layout itself (one column per 16-lane row group, unknowns
-// broadcast by shuffles), with the block's factor staged in LDS.
+// right-hand operand.  The tile's own entries (of G or of the right-hand sides)
+// are loaded straight into the accumulators before the contraction starts, and
+// the staged operand is stored negated, so those loads overlap the contraction's.
+// What is left is the 64 x 64 diagonal block: its four sub-blocks are finished in
+// order, each by MFMA products with the sub-blocks already finished and a solve
+// with the 16 x 16 diagonal block, also on MFMA: its inverse (computed once per
+// block row) applied, followed by one step of refinement, so the result keeps the
+// accuracy of a substitution.  The block's factor and inverses are staged in LDS.
 //
 // Factorization (k_potrf, one workgroup of four waves per element): for block row
 // R, U[R, :] = U[R, R]^{-T} (G[R, :] - U[:R, R]^T U[:R, :]).  The four tiles of the
@@ -86,14 +89,25 @@ __device__ __forceinline__ int blk_off(int t, int s) { return (t * NS + s - t * 
 // of any wave reads its step-q operand of sub-block s at (s * 4 + q) * 64 + lane.
 __device__ __forceinline__ int stage_idx(int s, int q, int kk, int i) { return (s * 4 + q) * 64 + kk * 16 + i; }
 
+// Barrier for the staged operand: it orders only the LDS accesses, so global loads in
+// flight (the next chunk's, the accumulators' initial values) stay in flight across it,
+// where a full __syncthreads would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Contraction over nch chunks of KC k, four waves in step: c[s] += sum_k A_s(i, k) B(k, j)
 // for the four sub-blocks s, on the waves with act (the waves run in step, so a wave that
-// needs fewer sub-blocks would only wait at the barrier; it computes them all).  load_a(ch, v) fetches this
-// thread's four entries of the left operand's chunk ch and put_a(buf, v) stores them
-// in the staging order; load_b(ch, v) fetches this lane's four right-hand entries
-// (k = 16 ch + 4 kk + q in step q).  The next chunk's global loads are in flight while
-// the MFMAs of the current one run; one barrier per chunk.  Every wave of the
-// workgroup calls it with the same nch.
+// needs fewer sub-blocks would only wait at the barrier; it computes them all), where A
+// is the operand as staged (negated by the callers).  load_a(ch, v) fetches this thread's
+// four entries of the left operand's chunk ch and put_a(buf, ch, v) stores them in the
+// staging order; load_b(ch, v) fetches this lane's four right-hand entries (k = 16 ch +
+// 4 kk + q in step q).  Both loads are unconditional (clamped into the matrix by the
+// callers), so nothing waits for them before their values are used.  The next chunk's
+// global loads are in flight while the MFMAs of the current one run; one barrier per
+// chunk.  Every wave of the workgroup calls it with the same nch.
 template <typename Real, typename FLA, typename FPA, typename FLB>
 __device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act, FLA load_a, FPA put_a,
                                                 FLB load_b, typename Mfma<Real>::acc (&c)[NS], int lane) {
@@ -101,15 +115,15 @@ __device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act,
   if (nch <= 0) return;
   Real va[4], vb[4], nb[4];
   load_a(0, va);
-  if (act) load_b(0, vb);
-  put_a(sA, va);
-  __syncthreads();
+  load_b(0, vb);
+  put_a(sA, 0, va);
+  lds_barrier();
   for (int64_t ch = 0; ch < nch; ++ch) {
     const Real* cur = sA + (ch & 1) * CH;
     const bool more = ch + 1 < nch;
     if (more) {
       load_a(ch + 1, va);
-      if (act) load_b(ch + 1, nb);
+      load_b(ch + 1, nb);
     }
     if (act) {
 #pragma unroll
@@ -118,11 +132,11 @@ __device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act,
         for (int s = 0; s < NS; ++s) c[s] = M::mac(cur[(s * 4 + q) * 64 + lane], vb[q], c[s]);
     }
     if (more) {
-      put_a(sA + ((ch + 1) & 1) * CH, va);
+      put_a(sA + ((ch + 1) & 1) * CH, ch + 1, va);
 #pragma unroll
       for (int q = 0; q < 4; ++q) vb[q] = nb[q];
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -147,55 +161,90 @@ __device__ __forceinline__ void sub_nn(typename Mfma<Real>::acc& v, const Real* 
   for (int q = 0; q < 4; ++q) v = M::mac(-T[i * LDB + M::row(g, q)], x[q], v);
 }
 
-// T^T x = v in place for the staged upper triangular block T (rd[k] = 1 / T[k][k]), v in
-// the accumulator layout (the 16 right-hand sides are the columns j = lane % 16).  Step
-// k finishes unknown k with its reciprocal pivot, broadcasts it along its column and
-// removes it from the rows below.  Unknowns from row h on (past the matrix) are set to
-// zero so that they reach no valid row.
+// A staged diagonal block holds U_ss (upper triangle and diagonal) and its inverse
+// V = U_ss^{-1} transposed (strictly lower triangle: V[k][i] at row i, column k), with
+// rd[k] = 1 / U_ss[k][k] = V[k][k].  Rows and columns past the matrix are the identity.
+// The MFMA left operands of step q for lane (i, g), k = row(g, q):
 template <typename Real>
-__device__ __forceinline__ void subst_fwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int h,
-                                          int lane) {
-  typedef Mfma<Real> M;
-  const int g = lane >> 4, j = lane & 15;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int gk = M::grp(k), rk = M::reg(k);
-    Real x = __shfl(v[rk] * rd[k], gk * 16 + j);
-    if (k >= h) x = Real(0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = M::row(g, r);
-      v[r] -= (m > k ? T[k * LDB + m] : Real(0)) * x;
-    }
-    if (g == gk) v[rk] = x;
-    __builtin_amdgcn_sched_barrier(0);   // keep the steps' coefficient loads from piling up in registers
-  }
+__device__ __forceinline__ Real op_vt(const Real* T, const Real* rd, int i, int k) {   // V^T[i][k]
+  return k < i ? T[i * LDB + k] : (k == i ? rd[i] : Real(0));
+}
+template <typename Real>
+__device__ __forceinline__ Real op_v(const Real* T, const Real* rd, int i, int k) {    // V[i][k]
+  return k > i ? T[k * LDB + i] : (k == i ? rd[i] : Real(0));
 }
 
-// T x = v in place (T, rd, h as above), bottom up.
+// U_ss^T x = v in place (v in the accumulator layout, the 16 right-hand sides are the
+// columns j = lane % 16): x0 = V^T v, then x = x0 + V^T (v - U_ss^T x0).
 template <typename Real>
-__device__ __forceinline__ void subst_bwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int h,
-                                          int lane) {
+__device__ __forceinline__ void solve_fwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int lane) {
   typedef Mfma<Real> M;
-  const int g = lane >> 4, j = lane & 15;
+  typedef typename M::acc acc;
+  const int i = lane & 15, g = lane >> 4;
+  Real av[4], au[4];
 #pragma unroll
-  for (int k = NB - 1; k >= 0; --k) {
-    const int gk = M::grp(k), rk = M::reg(k);
-    Real x = __shfl(v[rk] * rd[k], gk * 16 + j);
-    if (k >= h) x = Real(0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = M::row(g, r);
-      v[r] -= (m < k ? T[m * LDB + k] : Real(0)) * x;
-    }
-    if (g == gk) v[rk] = x;
-    __builtin_amdgcn_sched_barrier(0);
+  for (int q = 0; q < 4; ++q) {
+    const int k = M::row(g, q);
+    av[q] = op_vt(T, rd, i, k);
+    au[q] = k <= i ? -T[k * LDB + i] : Real(0);   // -U_ss^T[i][k]
   }
+  acc x = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);      // residual
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  v = x;
+}
+
+// U_ss x = v in place: x0 = V v, then x = x0 + V (v - U_ss x0).
+template <typename Real>
+__device__ __forceinline__ void solve_bwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int lane) {
+  typedef Mfma<Real> M;
+  typedef typename M::acc acc;
+  const int i = lane & 15, g = lane >> 4;
+  Real av[4], au[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = M::row(g, q);
+    av[q] = op_v(T, rd, i, k);
+    au[q] = k >= i ? -T[i * LDB + k] : Real(0);   // -U_ss[i][k]
+  }
+  acc x = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  v = x;
+}
+
+// Lane j < 16 of one wave: column j of V = U_ss^{-1} by back substitution against the
+// rows of U_ss (read from the staged block, the same for every lane), written
+// transposed into the block's strictly lower triangle.  Only this wave touches the
+// block meanwhile; its LDS accesses complete in order.
+template <typename Real>
+__device__ __forceinline__ void invert_block(Real* T, const Real* rd, int j) {
+  Real z[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) z[i] = i == j ? rd[i] : Real(0);
+#pragma unroll
+  for (int i = NB - 2; i >= 0; --i) {
+    Real d = Real(0);
+#pragma unroll
+    for (int k = i + 1; k < NB; ++k) d += T[i * LDB + k] * z[k];
+    if (i < j) z[i] = -rd[i] * d;
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < j) T[j * LDB + i] = z[i];
 }
 
 // Left operand "columns of U": chunk ch of U[k][r0 + r], k = 16 ch + .., r < 64 (columns
 // past n clamped to the last; rows past the matrix only reach output rows that are never
-// stored).  Thread t takes column r0 + t / 4, four consecutive k.
+// stored), staged negated.  Thread t takes column r0 + t / 4, four consecutive k.
 template <typename Real>
 struct ColsOperand {
   const Real* col;
@@ -212,14 +261,15 @@ struct ColsOperand {
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = col[KC * ch + kq + q];
   }
-  __device__ __forceinline__ void put(Real* buf, const Real (&v)[4]) const {
+  __device__ __forceinline__ void put(Real* buf, int64_t, const Real (&v)[4]) const {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) buf[stage_idx(s, q, kk, i)] = v[q];
+    for (int q = 0; q < 4; ++q) buf[stage_idx(s, q, kk, i)] = -v[q];
   }
 };
 
 // Left operand "rows of U": chunk ch of U[r0 + r][k], k = k0 + 16 ch + .. (zero from kend
-// on), r < 64.  Thread t takes column k0 + 16 ch + t / 16, four consecutive rows.
+// on: the load is clamped to the last column and the value dropped when it is staged),
+// r < 64, staged negated.  Thread t takes column k0 + 16 ch + t / 16, four consecutive rows.
 template <typename Real>
 struct RowsOperand {
   const Real* u;
@@ -228,30 +278,27 @@ struct RowsOperand {
   __device__ RowsOperand(const Real* u_, int64_t r0_, int64_t k0_, int64_t kend_, int tid)
       : u(u_), r0(r0_), k0(k0_), kend(kend_), kc(tid >> 4), rq(4 * (tid & 15)) {}
   __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
-    const int64_t k = k0 + KC * ch + kc;
-    const bool ok = k < kend;
-    const Real* p = u + colp(ok ? k : kend - 1) + r0 + rq;
+    const Real* p = u + colp(std::min(k0 + KC * ch + kc, kend - 1)) + r0 + rq;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = ok ? p[m] : Real(0);
+    for (int m = 0; m < 4; ++m) v[m] = p[m];
   }
-  __device__ __forceinline__ void put(Real* buf, const Real (&v)[4]) const {
+  __device__ __forceinline__ void put(Real* buf, int64_t ch, const Real (&v)[4]) const {
+    const bool ok = k0 + KC * ch + kc < kend;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int r = rq + m;
-      buf[stage_idx(r >> 4, kc & 3, kc >> 2, r & 15)] = v[m];
+      buf[stage_idx(r >> 4, kc & 3, kc >> 2, r & 15)] = ok ? -v[m] : Real(0);
     }
   }
 };
 
-// Right operand: this lane's column pb, k = k0 + 16 ch + 4 kk + q (zero from kend on).
+// Right operand: this lane's column pb, k = k0 + 16 ch + 4 kk + q, clamped to kend - 1 (past
+// kend the left operand is staged as zero, which drops these finite entries).
 template <typename Real>
 __device__ __forceinline__ void load_rhs(const Real* pb, int64_t k0, int64_t kend, int64_t ch, int lane, Real (&v)[4]) {
   const int64_t kb = k0 + KC * ch + 4 * (lane >> 4);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t k = kb + q;
-    v[q] = k < kend ? pb[k] : Real(0);
-  }
+  for (int q = 0; q < 4; ++q) v[q] = pb[std::min(kb + q, kend - 1)];
 }
 
 template <typename Real>
@@ -260,24 +307,32 @@ __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t 
   typedef Mfma<Real> M;
   typedef typename M::acc acc;
   __shared__ Real s_U[NBLK * NB * LDB];     // U on the diagonal block of the block row, blocks (t <= s)
-  __shared__ Real s_A[2 * CH];              // staged left operand (two chunks); the diagonal tile being
-                                            // factored borrows the first
+  __shared__ Real s_A[2 * CH];              // staged left operand (two chunks)
   __shared__ Real s_rd[BR];                 // reciprocal pivots of the diagonal block
   __shared__ int s_fail;
   const int64_t e = blockIdx.x;
   if (e >= n_elem) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, wv = tid >> 6;
   Real* a = ap + e * (n * (n + 1) / 2);
-  Real* s_S = s_A;
   const acc zero = {0, 0, 0, 0};
+  // The lane index is passed through an opaque copy at the top of every loop iteration:
+  // otherwise the compiler computes every lane-dependent constant (LDS offsets, masks,
+  // identity entries) once before the loops and keeps them, spilled, for the whole kernel.
+  int lane, li, lg;
+  auto relane = [&]() {
+    int l = tid & 63;
+    asm volatile("" : "+v"(l));
+    lane = l;
+    li = l & 15;
+    lg = l >> 4;
+  };
 
-  // S = G - S on this lane's accumulator slots (rows r0 + 16 s + .., column cb + lane % 16)
-  auto gram_minus = [&](int64_t r0, int s, int64_t cb, acc& S) {
+  // G on this lane's accumulator slots (rows r0 + 16 s + .., column cb + lane % 16)
+  auto gram_load = [&](int64_t r0, int s, int64_t cb, acc& S) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = r0 + NB * s + M::row(lg, r), col = cb + li;
-      const Real g = (row <= col && col < n) ? a[colp(col) + row] : Real(0);
-      S[r] = g - S[r];
+      S[r] = (row <= col && col < n) ? a[colp(col) + row] : Real(0);
     }
   };
   auto store = [&](int64_t r0, int s, int64_t cb, const acc& S) {
@@ -288,102 +343,138 @@ __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t 
     }
   };
   auto blk = [&](int t, int s) { return s_U + blk_off(t, s); };
-  // S = U[:r0, R]^T U[:r0, cb ..] (active waves)
+  // a staged 16 x 16 block to and from the accumulator layout
+  auto put_block = [&](Real* T, const acc& v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[M::row(lg, r) * LDB + li] = v[r];
+  };
+  auto get_block = [&](const Real* T, acc& v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = T[M::row(lg, r) * LDB + li];
+  };
+  // S -= U[:r0, R]^T U[:r0, cb ..] (active waves)
   auto contract = [&](int64_t r0, int64_t cb, bool act, acc (&S)[NS]) {
     const ColsOperand<Real> A(a, n, r0, tid);
     const Real* pb = a + colp(std::min<int64_t>(cb + li, n - 1));
     contract_staged<Real>(
         s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-        [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+        [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
         [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(pb, 0, r0, ch, lane, v); }, S, lane);
   };
 
   for (int64_t r0 = 0; r0 < n; r0 += BR) {
     const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));   // sub-blocks in this block row
-    // ---- the diagonal block, wave wv on columns r0 + 16 wv ..
+    relane();
+    // ---- the diagonal block: its contraction, wave wv on columns r0 + 16 wv .., leaves the
+    // ten blocks on or above the diagonal in LDS
     {
       const bool have = wv < nsb;
       const int64_t cb = r0 + NB * wv;
       acc S[NS] = {zero, zero, zero, zero};
+      if (have) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (s <= wv) gram_load(r0, s, cb, S[s]);
+      }
       contract(r0, cb, have, S);            // (the sub-blocks below the diagonal go unused)
       if (have) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-          if (s <= wv) gram_minus(r0, s, cb, S[s]);
+          if (s <= wv) put_block(blk(s, wv), S[s]);
       }
+    }
+    __syncthreads();
+    // ---- its Cholesky factor in LDS, right-looking over the 16 x 16 blocks: factor block
+    // (s, s), finish blocks (s, t > s) with it, remove row s from the blocks (t, u), s < t <= u
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        if (s >= nsb) break;
-        const int h = int(std::min<int64_t>(NB, n - r0 - NB * s));
-        if (have && wv >= s) {
+    for (int s = 0; s < NS; ++s) {
+      if (s >= nsb) break;
+      const int h = int(std::min<int64_t>(NB, n - r0 - NB * s));
+      const int64_t ib = r0 + NB * s;
+      if (wv == 0 && lane < NB) {           // unblocked Cholesky of block (s, s), one column per lane
+        const int j = lane;
+        Real* T = blk(s, s);
+        Real cl[NB];
 #pragma unroll
-          for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
-          if (wv == s) {
+        for (int i = 0; i < NB; ++i) cl[i] = T[i * LDB + j];
+        int fail = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) s_S[M::row(lg, r) * (NB + 1) + li] = S[s][r];
-          }
-        }
-        __syncthreads();
-        if (wv == s && lane < NB) {         // unblocked Cholesky of the diagonal tile, one column per lane
-          const int j = lane;
-          Real cl[NB];
+        for (int k = 0; k < NB; ++k) {
+          if (k < h && !fail) {             // uniform: h and the pivot are the same in every lane
+            const Real d = __shfl(cl[k], k);
+            if (!(d > Real(0))) {
+              fail = k + 1;
+            } else {
+              const Real ukk = sqrt(d);
+              cl[k] = j == k ? ukk : cl[k] / ukk;   // row k of U
 #pragma unroll
-          for (int i = 0; i < NB; ++i) cl[i] = s_S[i * (NB + 1) + j];
-          int fail = 0;
-#pragma unroll
-          for (int k = 0; k < NB; ++k) {
-            if (k < h && !fail) {           // uniform: h and the pivot are the same in every lane
-              const Real d = __shfl(cl[k], k);
-              if (!(d > Real(0))) {
-                fail = k + 1;
-              } else {
-                const Real ukk = sqrt(d);
-                cl[k] = j == k ? ukk : cl[k] / ukk;   // row k of U
-#pragma unroll
-                for (int i = k + 1; i < NB; ++i) cl[i] -= __shfl(cl[k], i) * cl[k];
-              }
+              for (int i = k + 1; i < NB; ++i) cl[i] -= __shfl(cl[k], i) * cl[k];
             }
           }
-          const int64_t ib = r0 + NB * s;
-          if (j < h && (!fail || j < fail - 1)) {  // on failure the columns before the failing one are final
-            Real* dst = a + colp(ib + j) + ib;
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-              if (i <= j) dst[i] = cl[i];
-          }
-#pragma unroll
-          for (int i = 0; i < NB; ++i) blk(s, s)[i * LDB + j] = i <= j ? cl[i] : Real(0);
-          s_rd[NB * s + j] = j < h ? Real(1) / cl[j] : Real(1);
-          if (j == 0) s_fail = fail ? int(ib) + fail : 0;
         }
-        __syncthreads();
-        if (s_fail) {
-          if (tid == 0 && info) info[e] = s_fail;
-          return;
-        }
-        if (have && wv > s) {               // U[s, s]^T x = S[s]: this tile's rows of sub-block s
-          subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, h, lane);
-          store(r0, s, cb, S[s]);
+        if (j < h && (!fail || j < fail - 1)) {    // on failure the columns before the failing one are final
+          Real* dst = a + colp(ib + j) + ib;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) blk(s, wv)[M::row(lg, r) * LDB + li] = S[s][r];
+          for (int i = 0; i < NB; ++i)
+            if (i <= j) dst[i] = cl[i];
+        }
+        // U_ss (columns past the matrix the identity), then its inverse below the diagonal
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i <= j) T[i * LDB + j] = j < h ? cl[i] : Real(i == j ? 1 : 0);
+        s_rd[NB * s + j] = j < h ? Real(1) / cl[j] : Real(1);
+        if (j == 0) s_fail = fail ? int(ib) + fail : 0;
+        invert_block<Real>(T, s_rd + NB * s, j);
+      }
+      __syncthreads();
+      if (s_fail) {
+        if (tid == 0 && info) info[e] = s_fail;
+        return;
+      }
+      if (wv < nsb - 1 - s) {               // block (s, t): U_ss^T x = C(s, t)
+        const int t = s + 1 + wv;
+        acc x;
+        get_block(blk(s, t), x);
+        solve_fwd<Real>(x, blk(s, s), s_rd + NB * s, lane);
+        put_block(blk(s, t), x);
+        store(r0, s, r0 + NB * t, x);
+      }
+      __syncthreads();
+      const int m = nsb - 1 - s;            // trailing blocks (t, u), s < t <= u < nsb
+      if (m > 0) {
+        for (int idx = wv; idx < m * (m + 1) / 2; idx += NW) {
+          int t = 0, u = idx;
+          while (u >= m - t) { u -= m - t; ++t; }
+          t += s + 1;
+          u += t;
+          acc c, x;
+          get_block(blk(t, u), c);
+          get_block(blk(s, u), x);
+          sub_tn<Real>(c, blk(s, t), x, lane);
+          put_block(blk(t, u), c);
         }
         __syncthreads();
       }
     }
     // ---- the tiles right of the diagonal block, four at a time (one per wave)
     for (int64_t cg = r0 + BR; cg < n; cg += BR) {
+      relane();
       const int64_t cb = cg + NB * wv;
       const bool act = cb < n;
       acc S[NS] = {zero, zero, zero, zero};
+      if (act) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (s < nsb) gram_load(r0, s, cb, S[s]);
+      }
       contract(r0, cb, act, S);
       if (act) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           if (s >= nsb) break;
-          gram_minus(r0, s, cb, S[s]);
 #pragma unroll
           for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
-          subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+          solve_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
           store(r0, s, cb, S[s]);
         }
       }
@@ -413,12 +504,24 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
   const int64_t wg = xcd_major(blockIdx.x, gridDim.x);
   const int64_t e = e0 + wg / nblk, cbk = wg % nblk;
   if (e >= n_elem) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, wv = tid >> 6;
   const Real* u = up + e * (n * (n + 1) / 2);
   const int64_t c0 = cbk * BR + NB * wv;    // this wave's first right-hand side
   const bool act = c0 < nrhs;
-  const bool colok = c0 + li < nrhs;
-  Real* xc = b + e * n * nrhs + std::min<int64_t>(c0 + li, nrhs - 1) * n;   // this lane's right-hand side
+  // lane index through an opaque copy per block row (lane constants are not kept live across
+  // the whole kernel)
+  int lane, li, lg;
+  bool colok;
+  Real* xc;                                 // this lane's right-hand side
+  auto relane = [&]() {
+    int l = tid & 63;
+    asm volatile("" : "+v"(l));
+    lane = l;
+    li = l & 15;
+    lg = l >> 4;
+    colok = c0 + li < nrhs;
+    xc = b + e * n * nrhs + std::min<int64_t>(c0 + li, nrhs - 1) * n;
+  };
   const acc zero = {0, 0, 0, 0};
   auto blk = [&](int t, int s) { return s_U + blk_off(t, s); };
 
@@ -436,12 +539,16 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
       if (t == s && r == c) s_rd[NB * t + r] = Real(1) / v;
     }
   };
-  auto rhs_minus = [&](int64_t r0, int s, acc& S) {
+  auto rhs_load = [&](int64_t r0, int s, acc& S) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = r0 + NB * s + M::row(lg, r);
-      S[r] = ((colok && row < n) ? xc[row] : Real(0)) - S[r];
+      S[r] = (colok && row < n) ? xc[row] : Real(0);
     }
+  };
+  // the inverses of the four diagonal blocks, one per wave (after the staging barrier)
+  auto invert = [&](int nsb) {
+    if (wv < nsb && lane < NB) invert_block<Real>(blk(wv, wv), s_rd + NB * wv, lane);
   };
   auto store = [&](int64_t r0, int s, const acc& S) {
 #pragma unroll
@@ -454,20 +561,23 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
   // U^T y = b, top down
   for (int64_t r0 = 0; r0 < n; r0 += BR) {
     const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));
+    relane();
     __syncthreads();                        // the previous block row is done with s_U
     stage(r0);
     acc S[NS] = {zero, zero, zero, zero};
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s < nsb) rhs_load(r0, s, S[s]);
+    }
+    __syncthreads();
+    invert(nsb);
     {
       const ColsOperand<Real> A(u, n, r0, tid);
       contract_staged<Real>(
           s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-          [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+          [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
           [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, 0, r0, ch, lane, v); }, S, lane);
-    }
-    if (act) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (s < nsb) rhs_minus(r0, s, S[s]);
     }
     __syncthreads();
     if (act) {
@@ -476,7 +586,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
         if (s >= nsb) break;
 #pragma unroll
         for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
-        subst_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+        solve_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
         store(r0, s, S[s]);
       }
     }
@@ -484,21 +594,24 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
   // U x = y, bottom up
   for (int64_t r0 = ((n - 1) / BR) * BR; r0 >= 0; r0 -= BR) {
     const int nsb = int(std::min<int64_t>(NS, (n - r0 + NB - 1) / NB));
+    relane();
     __syncthreads();
     stage(r0);
     acc S[NS] = {zero, zero, zero, zero};
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s < nsb) rhs_load(r0, s, S[s]);
+    }
+    __syncthreads();
+    invert(nsb);
     {
       const int64_t k0 = r0 + BR;
       const RowsOperand<Real> A(u, r0, k0, n, tid);
       contract_staged<Real>(
           s_A, k0 < n ? (n - k0 + KC - 1) / KC : 0, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-          [&](Real* buf, const Real(&v)[4]) { A.put(buf, v); },
+          [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
           [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, k0, n, ch, lane, v); }, S, lane);
-    }
-    if (act) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (s < nsb) rhs_minus(r0, s, S[s]);
     }
     __syncthreads();
     if (act) {
@@ -508,7 +621,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
 #pragma unroll
         for (int t = s + 1; t < NS; ++t)
           if (t < nsb) sub_nn<Real>(S[s], blk(s, t), S[t], lane);
-        subst_bwd<Real>(S[s], blk(s, s), s_rd + NB * s, int(std::min<int64_t>(NB, n - r0 - NB * s)), lane);
+        solve_bwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
         store(r0, s, S[s]);
       }
     }
