@@ -249,8 +249,9 @@ int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copi
  * when the leading minor of order k of that element is not positive
  * definite; then columns 0..k-2 of its U are final and the rest of its
  * storage is unspecified.  Device memory of the precision prec; asynchronous
- * on stream.  Errors: DPG_EINVAL (n outside [1, 65536], n_elem < 0, null ap,
- * prec), DPG_ENOTINIT, DPG_EHIP. */
+ * on stream.  n is at most 16384 (the kernels address one element's packed
+ * matrix with 32-bit byte offsets).  Errors: DPG_EINVAL (n outside [1, 16384],
+ * n_elem < 0, null ap, prec), DPG_ENOTINIT, DPG_EHIP. */
 int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap, int32_t* info, int prec,
                         void* stream);
 
@@ -259,7 +260,7 @@ int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap,
  * n x nrhs blocks (leading dimension n, element e at b + e n nrhs) and is
  * overwritten with X (LAPACK dpptrs).  up and b are device memory of the
  * precision prec and must not overlap.  Asynchronous on stream.  Errors:
- * DPG_EINVAL (n outside [1, 65536], nrhs outside [1, 2^26], n_elem < 0, null
+ * DPG_EINVAL (n outside [1, 16384], nrhs outside [1, 2^26], n_elem < 0, null
  * pointers, overlap, prec), DPG_ENOTINIT, DPG_EHIP. */
 int dpg_cholesky_solve_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, const void* up, int64_t nrhs, void* b,
                               int prec, void* stream);

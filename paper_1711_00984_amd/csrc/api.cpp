@@ -277,7 +277,7 @@ int dpg_replicate_blocks(const dpg_ctx* ctx, int64_t n_elem, int64_t n, int copi
 int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap, int32_t* info, int prec,
                         void* stream) {
   if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
-  if (n_elem < 0 || n < 1 || n > 65536) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
+  if (n_elem < 0 || n < 1 || n > 16384) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
   if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
   if (n_elem == 0) return DPG_OK;
   if (!ap) return fail(DPG_EINVAL, "packed Grams are NULL");
@@ -288,7 +288,7 @@ int dpg_cholesky_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, void* ap,
 int dpg_cholesky_solve_packed(const dpg_ctx* ctx, int64_t n_elem, int64_t n, const void* up, int64_t nrhs, void* b,
                               int prec, void* stream) {
   if (!ctx || !ctx->d_tab64) return fail(DPG_ENOTINIT, "null or destroyed context");
-  if (n_elem < 0 || n < 1 || n > 65536) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
+  if (n_elem < 0 || n < 1 || n > 16384) return fail(DPG_EINVAL, "n_elem=%lld, n=%lld", (long long)n_elem, (long long)n);
   if (nrhs < 1 || nrhs > (int64_t(1) << 26)) return fail(DPG_EINVAL, "nrhs=%lld", (long long)nrhs);
   if (prec != DPG_FP64 && prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", prec);
   if (n_elem == 0) return DPG_OK;

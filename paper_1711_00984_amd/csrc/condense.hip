@@ -98,45 +98,82 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Buffer resource over count entries at p (the loads below go through the vector
+// memory path with a scalar base, a 32-bit per-lane byte offset and a scalar offset,
+// so a chunk step costs no per-lane address arithmetic; reads at or past count
+// entries, vector offset included, return zero).  Callers keep count * sizeof(Real)
+// below 2^31.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+template <typename Real>
+__device__ __forceinline__ Rsrc make_rsrc(const Real* p, int64_t count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(p), 0, int(count * int64_t(sizeof(Real))), 0x00020000);
+}
+// Four consecutive entries at byte offset voff + soff.
+__device__ __forceinline__ void load4(Rsrc r, uint32_t voff, uint32_t soff, double (&v)[4]) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 x = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  const d2 y = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0));
+  v[0] = x[0];
+  v[1] = x[1];
+  v[2] = y[0];
+  v[3] = y[1];
+}
+__device__ __forceinline__ void load4(Rsrc r, uint32_t voff, uint32_t soff, float (&v)[4]) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 x = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = x[q];
+}
+
+// Make the accumulators' initial loads complete here, so that the loop after it has no
+// load of them in flight (the wait would otherwise sit inside the loop and drain the
+// next chunk's loads on every iteration).
+template <typename Real>
+__device__ __forceinline__ void settle(const typename Mfma<Real>::acc& v) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(v[r]));
+}
+
 // Contraction over nch chunks of KC k, four waves in step: c[s] += sum_k A_s(i, k) B(k, j)
 // for the four sub-blocks s, on the waves with act (the waves run in step, so a wave that
 // needs fewer sub-blocks would only wait at the barrier; it computes them all), where A
-// is the operand as staged (negated by the callers).  load_a(ch, v) fetches this thread's
-// four entries of the left operand's chunk ch and put_a(buf, ch, v) stores them in the
-// staging order; load_b(ch, v) fetches this lane's four right-hand entries (k = 16 ch +
-// 4 kk + q in step q).  Both loads are unconditional (clamped into the matrix by the
-// callers), so nothing waits for them before their values are used.  The next chunk's
-// global loads are in flight while the MFMAs of the current one run; one barrier per
-// chunk.  Every wave of the workgroup calls it with the same nch.
-template <typename Real, typename FLA, typename FPA, typename FLB>
-__device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act, FLA load_a, FPA put_a,
-                                                FLB load_b, typename Mfma<Real>::acc (&c)[NS], int lane) {
+// is the operand as staged (negated by the callers).  A.load(ch, v) fetches this
+// thread's four entries of the left operand's chunk ch and A.put(buf, ch, v) stores them
+// in the staging order; B.load(ch, v) fetches this lane's four right-hand entries (k =
+// 16 ch + 4 kk + q in step q).  The next chunk's loads are in flight while the MFMAs of
+// the current one run; one barrier per chunk.  Unrolled by two, the register sets for
+// the chunks in flight alternate, so no value in flight is ever copied (a copy would wait
+// for it).  Every wave of the workgroup calls it with the same nch.
+template <typename Real, typename TA, typename TB>
+__device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act, const TA& A, const TB& B,
+                                                typename Mfma<Real>::acc (&c)[NS], int lane) {
   typedef Mfma<Real> M;
   if (nch <= 0) return;
-  Real va[4], vb[4], nb[4];
-  load_a(0, va);
-  load_b(0, vb);
-  put_a(sA, 0, va);
+  Real a0[4], a1[4], b0[4], b1[4];
+  A.load(0, a0);
+  B.load(0, b0);
+  A.put(sA, 0, a0);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) settle<Real>(c[s]);
   lds_barrier();
-  for (int64_t ch = 0; ch < nch; ++ch) {
-    const Real* cur = sA + (ch & 1) * CH;
+  auto step = [&](int64_t ch, const Real* cur, Real* nxt, const Real(&bc)[4], Real(&an)[4], Real(&bn)[4]) {
     const bool more = ch + 1 < nch;
-    if (more) {
-      load_a(ch + 1, va);
-      load_b(ch + 1, nb);
-    }
+    // unconditional: a branch around the loads would make the wait before the MFMAs cover
+    // them too (the chunk past the end reads entries in range or zeros, and goes unused)
+    A.load(ch + 1, an);
+    B.load(ch + 1, bn);
     if (act) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int s = 0; s < NS; ++s) c[s] = M::mac(cur[(s * 4 + q) * 64 + lane], vb[q], c[s]);
+        for (int s = 0; s < NS; ++s) c[s] = M::mac(cur[(s * 4 + q) * 64 + lane], bc[q], c[s]);
     }
-    if (more) {
-      put_a(sA + ((ch + 1) & 1) * CH, ch + 1, va);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) vb[q] = nb[q];
-    }
+    if (more) A.put(nxt, ch + 1, an);
     lds_barrier();
+  };
+  for (int64_t ch = 0; ch < nch; ch += 2) {
+    step(ch, sA, sA + CH, b0, a1, b1);
+    if (ch + 1 < nch) step(ch + 1, sA + CH, sA, b1, a0, b0);
   }
 }
 
@@ -247,19 +284,19 @@ __device__ __forceinline__ void invert_block(Real* T, const Real* rd, int j) {
 // stored), staged negated.  Thread t takes column r0 + t / 4, four consecutive k.
 template <typename Real>
 struct ColsOperand {
-  const Real* col;
-  int kq, s, i, kk;
+  Rsrc rs;
+  uint32_t vo;
+  int s, i, kk;
   __device__ ColsOperand(const Real* u, int64_t n, int64_t r0, int tid) {
     const int r = tid >> 2;
-    kq = 4 * (tid & 3);
-    col = u + colp(std::min<int64_t>(r0 + r, n - 1));
+    kk = tid & 3;
+    rs = make_rsrc(u, n * (n + 1) / 2);
+    vo = uint32_t((colp(std::min<int64_t>(r0 + r, n - 1)) + 4 * kk) * int64_t(sizeof(Real)));
     s = r >> 4;
     i = r & 15;
-    kk = tid & 3;
   }
   __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = col[KC * ch + kq + q];
+    load4(rs, vo, uint32_t(KC * ch * int64_t(sizeof(Real))), v);
   }
   __device__ __forceinline__ void put(Real* buf, int64_t, const Real (&v)[4]) const {
 #pragma unroll
@@ -272,15 +309,14 @@ struct ColsOperand {
 // r < 64, staged negated.  Thread t takes column k0 + 16 ch + t / 16, four consecutive rows.
 template <typename Real>
 struct RowsOperand {
-  const Real* u;
+  Rsrc rs;
   int64_t r0, k0, kend;
   int kc, rq;
-  __device__ RowsOperand(const Real* u_, int64_t r0_, int64_t k0_, int64_t kend_, int tid)
-      : u(u_), r0(r0_), k0(k0_), kend(kend_), kc(tid >> 4), rq(4 * (tid & 15)) {}
+  __device__ RowsOperand(const Real* u, int64_t n, int64_t r0_, int64_t k0_, int64_t kend_, int tid)
+      : rs(make_rsrc(u, n * (n + 1) / 2)), r0(r0_), k0(k0_), kend(kend_), kc(tid >> 4), rq(4 * (tid & 15)) {}
   __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
-    const Real* p = u + colp(std::min(k0 + KC * ch + kc, kend - 1)) + r0 + rq;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = p[m];
+    const int64_t k = std::min(k0 + KC * ch + kc, kend - 1);
+    load4(rs, uint32_t((colp(k) + r0 + rq) * int64_t(sizeof(Real))), 0, v);
   }
   __device__ __forceinline__ void put(Real* buf, int64_t ch, const Real (&v)[4]) const {
     const bool ok = k0 + KC * ch + kc < kend;
@@ -292,14 +328,25 @@ struct RowsOperand {
   }
 };
 
-// Right operand: this lane's column pb, k = k0 + 16 ch + 4 kk + q, clamped to kend - 1 (past
-// kend the left operand is staged as zero, which drops these finite entries).
-template <typename Real>
-__device__ __forceinline__ void load_rhs(const Real* pb, int64_t k0, int64_t kend, int64_t ch, int lane, Real (&v)[4]) {
-  const int64_t kb = k0 + KC * ch + 4 * (lane >> 4);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = pb[std::min(kb + q, kend - 1)];
-}
+// Right operand: entries k = k0 + 16 ch + 4 kk + q of this lane's column, which starts at
+// entry col of the resource.  With INRANGE every k read lies in the column (the chunk
+// step goes in the scalar offset); otherwise the whole offset is in the vector part, so
+// that a read past the resource returns zero (past the column, reads within the resource
+// return finite entries, which the zero left operand drops).
+template <typename Real, bool INRANGE>
+struct RhsOperand {
+  Rsrc rs;
+  uint32_t vo;
+  __device__ RhsOperand(Rsrc r, int64_t col, int64_t k0, int lane)
+      : rs(r), vo(uint32_t((col + k0 + 4 * (lane >> 4)) * int64_t(sizeof(Real)))) {}
+  __device__ __forceinline__ void load(int64_t ch, Real (&v)[4]) const {
+    const uint32_t step = uint32_t(KC * ch * int64_t(sizeof(Real)));
+    if (INRANGE)
+      load4(rs, vo, step, v);
+    else
+      load4(rs, vo + step, 0, v);
+  }
+};
 
 template <typename Real>
 __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t n, int64_t n_elem,
@@ -355,11 +402,8 @@ __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t 
   // S -= U[:r0, R]^T U[:r0, cb ..] (active waves)
   auto contract = [&](int64_t r0, int64_t cb, bool act, acc (&S)[NS]) {
     const ColsOperand<Real> A(a, n, r0, tid);
-    const Real* pb = a + colp(std::min<int64_t>(cb + li, n - 1));
-    contract_staged<Real>(
-        s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-        [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
-        [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(pb, 0, r0, ch, lane, v); }, S, lane);
+    const RhsOperand<Real, true> B(A.rs, colp(std::min<int64_t>(cb + li, n - 1)), 0, lane);
+    contract_staged<Real>(s_A, r0 / KC, act, A, B, S, lane);
   };
 
   for (int64_t r0 = 0; r0 < n; r0 += BR) {
@@ -522,6 +566,10 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
     colok = c0 + li < nrhs;
     xc = b + e * n * nrhs + std::min<int64_t>(c0 + li, nrhs - 1) * n;
   };
+  // this workgroup's right-hand sides (at most 64 columns) as one buffer resource
+  const int64_t wcols = std::min<int64_t>(BR, nrhs - cbk * BR);
+  const Rsrc xr = make_rsrc(b + e * n * nrhs + cbk * BR * n, wcols * n);
+  auto xcol = [&]() { return std::min<int64_t>(NB * wv + li, wcols - 1) * n; };   // this lane's, in it
   const acc zero = {0, 0, 0, 0};
   auto blk = [&](int t, int s) { return s_U + blk_off(t, s); };
 
@@ -574,10 +622,8 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
     invert(nsb);
     {
       const ColsOperand<Real> A(u, n, r0, tid);
-      contract_staged<Real>(
-          s_A, r0 / KC, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-          [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
-          [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, 0, r0, ch, lane, v); }, S, lane);
+      const RhsOperand<Real, true> B(xr, xcol(), 0, lane);
+      contract_staged<Real>(s_A, r0 / KC, act, A, B, S, lane);
     }
     __syncthreads();
     if (act) {
@@ -607,11 +653,9 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
     invert(nsb);
     {
       const int64_t k0 = r0 + BR;
-      const RowsOperand<Real> A(u, r0, k0, n, tid);
-      contract_staged<Real>(
-          s_A, k0 < n ? (n - k0 + KC - 1) / KC : 0, act, [&](int64_t ch, Real(&v)[4]) { A.load(ch, v); },
-          [&](Real* buf, int64_t ch, const Real(&v)[4]) { A.put(buf, ch, v); },
-          [&](int64_t ch, Real(&v)[4]) { load_rhs<Real>(xc, k0, n, ch, lane, v); }, S, lane);
+      const RowsOperand<Real> A(u, n, r0, k0, n, tid);
+      const RhsOperand<Real, false> B(xr, xcol(), k0, lane);
+      contract_staged<Real>(s_A, k0 < n ? (n - k0 + KC - 1) / KC : 0, act, A, B, S, lane);
     }
     __syncthreads();
     if (act) {

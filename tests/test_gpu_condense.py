@@ -198,6 +198,11 @@ def test_errors_and_empty(ctx, dpg):
     assert rc == dpg.EINVAL
     rc = dpg._lib.dpg_cholesky_packed(ctx.handle, 1, n, ap.data_ptr(), None, 7, None)
     assert rc == dpg.EINVAL
+    # one element's packed matrix must stay addressable with 32-bit byte offsets
+    rc = dpg._lib.dpg_cholesky_packed(ctx.handle, 1, 16385, ap.data_ptr(), None, 0, None)
+    assert rc == dpg.EINVAL
+    rc = dpg._lib.dpg_cholesky_solve_packed(ctx.handle, 1, 16385, ap.data_ptr(), 1, ap.data_ptr(), 0, None)
+    assert rc == dpg.EINVAL
 
 
 def test_benchmark_size_sampled(ctx, dpg):
