@@ -139,6 +139,8 @@ def main():
                          "(0: skip the serving measurement)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 4 GiB device copy (counter calibration)")
+    ap.add_argument("--condense-only", action="store_true",
+                    help="run only the condensation measurement (factor and solve of 1024 H1 p=7 Grams)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the elements are "
@@ -166,6 +168,10 @@ def main():
         return
 
     ctx = dpg.Context(p_max=11)
+    if a.condense_only:
+        print(json.dumps({"condense_h1_p7": run_condense(ctx, dpg, stream)}), flush=True)
+        ctx.close()
+        return
     E, space, p = 4096, "H1", 7
     X = torch.from_numpy(meshgen.perturbed_hexes(E, noise=0.15, seed=1712)).cuda()
     m = dpg.packed_len(space, p)
@@ -242,6 +248,50 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def run_condense(ctx, dpg, stream):
+    import numpy as np
+    import torch
+
+    import meshgen
+
+    # static condensation on the device: Cholesky factor of the benchmark's Grams in place, then
+    # G^{-1} B for 343 right-hand sides (the H1 trial space of order 6 of the Poisson example)
+    n_c, sp_c, p_c, nrhs_c = 1024, "H1", 7, 343
+    nn = dpg.gram_dim(sp_c, p_c)
+    mc = nn * (nn + 1) // 2
+    Xc = torch.from_numpy(meshgen.perturbed_hexes(n_c, noise=0.15, seed=1713)).cuda()
+    gsrc = ctx.gram(sp_c, p_c, Xc, stream=stream)
+    work = torch.empty_like(gsrc)
+    info = torch.empty(n_c, dtype=torch.int32, device="cuda")
+    fr = []
+    for it in range(6):
+        work.copy_(gsrc)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.cholesky(work, nn, info=info, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it:
+            fr.append(e0.elapsed_time(e1))
+    assert int(info.abs().sum()) == 0, "benchmark Grams must factor"
+    kf = float(np.mean(fr))
+    flops_f = n_c * (nn ** 3 / 3.0 + nn ** 2 / 2.0)
+    bmat = torch.randn(n_c, nrhs_c, nn, dtype=torch.float64, device="cuda")
+    w, pr = time_launches(lambda: ctx.cholesky_solve(work, nn, bmat, stream=stream), 3, 1, stream)
+    ks = float(np.mean(pr))
+    flops_s = n_c * 2.0 * nn * nn * nrhs_c
+    row = {
+        "n_elem": n_c, "n": nn, "nrhs": nrhs_c,
+        "cholesky_ms": round(kf, 3), "cholesky_tflops": round(flops_f / (kf * 1e-3) / 1e12, 2),
+        "cholesky_frac_fp64": round(flops_f / (kf * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+        "solve_ms": round(ks, 3), "solve_tflops": round(flops_s / (ks * 1e-3) / 1e12, 2),
+        "solve_frac_fp64": round(flops_s / (ks * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    log(f"[bench] extra condense {row}")
+    del gsrc, work, bmat, Xc
+    torch.cuda.empty_cache()
+    return row
 
 
 def run_extra(ctx, dpg, stream, E, X, out64):
@@ -329,41 +379,7 @@ def run_extra(ctx, dpg, stream, E, X, out64):
         torch.cuda.empty_cache()
     res["aniso_orders"] = ani
 
-    # static condensation on the device: Cholesky factor of the benchmark's Grams in place, then
-    # G^{-1} B for 343 right-hand sides (the H1 trial space of order 6 of the Poisson example)
-    n_c, sp_c, p_c, nrhs_c = 1024, "H1", 7, 343
-    nn = dpg.gram_dim(sp_c, p_c)
-    mc = nn * (nn + 1) // 2
-    Xc = torch.from_numpy(meshgen.perturbed_hexes(n_c, noise=0.15, seed=1713)).cuda()
-    gsrc = ctx.gram(sp_c, p_c, Xc, stream=stream)
-    work = torch.empty_like(gsrc)
-    info = torch.empty(n_c, dtype=torch.int32, device="cuda")
-    fr = []
-    for it in range(6):
-        work.copy_(gsrc)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ctx.cholesky(work, nn, info=info, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        if it:
-            fr.append(e0.elapsed_time(e1))
-    assert int(info.abs().sum()) == 0, "benchmark Grams must factor"
-    kf = float(np.mean(fr))
-    flops_f = n_c * (nn ** 3 / 3.0 + nn ** 2 / 2.0)
-    bmat = torch.randn(n_c, nrhs_c, nn, dtype=torch.float64, device="cuda")
-    w, pr = time_launches(lambda: ctx.cholesky_solve(work, nn, bmat, stream=stream), 3, 1, stream)
-    ks = float(np.mean(pr))
-    flops_s = n_c * 2.0 * nn * nn * nrhs_c
-    res["condense_h1_p7"] = {
-        "n_elem": n_c, "n": nn, "nrhs": nrhs_c,
-        "cholesky_ms": round(kf, 3), "cholesky_tflops": round(flops_f / (kf * 1e-3) / 1e12, 2),
-        "cholesky_frac_fp64": round(flops_f / (kf * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
-        "solve_ms": round(ks, 3), "solve_tflops": round(flops_s / (ks * 1e-3) / 1e12, 2),
-        "solve_frac_fp64": round(flops_s / (ks * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
-    log(f"[bench] extra condense {res['condense_h1_p7']}")
-    del gsrc, work, bmat, Xc
-    torch.cuda.empty_cache()
+    res["condense_h1_p7"] = run_condense(ctx, dpg, stream)
     # adjoint graph coupling block (one constant matrix per order)
     cpl = ctx.adjoint_coupling(11)
     w, pr = time_launches(lambda: ctx.adjoint_coupling(11, out=cpl, stream=stream), 5, 1, stream)
