@@ -223,7 +223,7 @@ def main():
     torch.cuda.empty_cache()
     if a.extra:
         extra["batched_mixed_50000"] = run_mixed_full(ctx, dpg, stream)
-        extra["orders_p4_p8"] = run_orders(ctx, dpg, stream)
+        extra["orders_p4_p10"] = run_orders(ctx, dpg, stream)
         extra["scaling"] = run_scaling(ctx, dpg, stream)
         extra["latency"] = run_latency(ctx, dpg, stream)
     serving = None
@@ -526,7 +526,7 @@ def run_latency(ctx, dpg, stream, reps=200):
 
 
 def run_orders(ctx, dpg, stream, out_bytes=2 << 30):
-    """The metric's per-order figures: every space at p = 4..8 on the general
+    """The metric's per-order figures: every space at p = 4..10 on the general
     (quadrature) path, FP64, perturbed hexes (seed 7), about out_bytes of output per
     launch (at most 8192 elements), the shipped tuning table's schedules.  Each row:
     elements/s and the fraction of its roofline 1 / max(F / 78.6 TFLOP/s,
@@ -538,7 +538,7 @@ def run_orders(ctx, dpg, stream, out_bytes=2 << 30):
     import meshgen
     rows = []
     for space in ("H1", "HCURL", "HDIV", "L2"):
-        for p in range(4, 9):
+        for p in range(4, 11):
             m = dpg.packed_len(space, p)
             n = int(max(16, min(8192, out_bytes // (m * 8))))
             g = torch.from_numpy(meshgen.perturbed_hexes(n, seed=7)).cuda()
