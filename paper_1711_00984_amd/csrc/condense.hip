@@ -9,26 +9,29 @@
 // Both kernels go down the matrix in block rows of 64 (four 16-row sub-blocks).
 // A wave owns a 64 x 16 tile of the block row (four MFMA accumulators) and first
 // removes from it, in one contraction on FP64 or FP32 MFMA, everything the rows
-// above contribute; that contraction is almost all of the arithmetic.  Its k
-// steps are dealt so that each lane reads four consecutive entries of a packed
-// column (whole 128-byte runs per 16 lanes), and the four sub-blocks share the
-// right-hand operand.  The tile's own entries (of G or of the right-hand sides)
-// are loaded straight into the accumulators before the contraction starts, and
-// the staged operand is stored negated, so those loads overlap the contraction's.
-// What is left is the 64 x 64 diagonal block: its four sub-blocks are finished in
-// order, each by MFMA products with the sub-blocks already finished and a solve
-// with the 16 x 16 diagonal block, also on MFMA: its inverse (computed once per
-// block row) applied, followed by one step of refinement, so the result keeps the
-// accuracy of a substitution.  The block's factor and inverses are staged in LDS.
+// above contribute; that contraction is almost all of the arithmetic.  Its left
+// operand (64 rows of U, the same for every tile of the block row) is staged in
+// LDS once per workgroup, 16 k at a time, and shared by the four waves; the loads
+// go through buffer resources with offsets fixed for the whole contraction, and
+// each lane reads four consecutive entries of a packed column.  The tile's own
+// entries (of G or of the right-hand sides) are loaded straight into the
+// accumulators before the contraction starts, and the staged operand is stored
+// negated, so those loads overlap the contraction's.  What is left is the 64 x 64
+// diagonal block: its four sub-blocks are finished in order, each by MFMA
+// products with the sub-blocks already finished and a solve with the 16 x 16
+// diagonal block, also on MFMA: its inverse (computed once per block row)
+// applied, followed by one step of refinement, so the result keeps the accuracy
+// of a substitution.  The block's factor and inverses are staged in LDS.
 //
 // Factorization (k_potrf, one workgroup of four waves per element): for block row
-// R, U[R, :] = U[R, R]^{-T} (G[R, :] - U[:R, R]^T U[:R, :]).  The four tiles of the
-// diagonal block go first, one per wave, in step with barriers (the wave on the
-// diagonal factors its 16 x 16 tile, the waves to its right substitute with it);
-// the tiles right of the diagonal block then need nothing more from other waves
-// and go round robin.  Solve (k_potrs, one workgroup per element and 64
-// right-hand sides, 16 per wave): U^T y = b down the block rows, then U x = y up
-// them, the diagonal block of each block row staged in LDS.
+// R, U[R, :] = U[R, R]^{-T} (G[R, :] - U[:R, R]^T U[:R, :]).  The diagonal block
+// goes first: its contraction (one tile per wave) leaves its ten blocks on or above
+// the diagonal in LDS, where it is factored right-looking over the 16 x 16 blocks.
+// The tiles right of the diagonal block then go four at a time (one per wave), each
+// finished by its own wave with no further barrier.  Solve (k_potrs, one workgroup
+// per element and 64 right-hand sides, 16 per wave): U^T y = b down the block rows,
+// then U x = y up them, the diagonal block of each block row staged in LDS and its
+// four inverses computed by the four waves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,9 +103,10 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Buffer resource over count entries at p (the loads below go through the vector
 // memory path with a scalar base, a 32-bit per-lane byte offset and a scalar offset,
-// so a chunk step costs no per-lane address arithmetic; reads at or past count
-// entries, vector offset included, return zero).  Callers keep count * sizeof(Real)
-// below 2^31.
+// so a chunk step costs no per-lane address arithmetic).  The range check covers the
+// vector offset only: a read whose vector offset is at or past count entries returns
+// zero, while the scalar offset must keep every read inside the matrix by itself.
+// Callers keep count * sizeof(Real) below 2^31.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 template <typename Real>
 __device__ __forceinline__ Rsrc make_rsrc(const Real* p, int64_t count) {
@@ -159,9 +163,12 @@ __device__ __forceinline__ void contract_staged(Real* sA, int64_t nch, bool act,
   auto step = [&](int64_t ch, const Real* cur, Real* nxt, const Real(&bc)[4], Real(&an)[4], Real(&bn)[4]) {
     const bool more = ch + 1 < nch;
     // unconditional: a branch around the loads would make the wait before the MFMAs cover
-    // them too (the chunk past the end reads entries in range or zeros, and goes unused)
-    A.load(ch + 1, an);
-    B.load(ch + 1, bn);
+    // them too.  Past the last chunk the current one is loaded again (unused): the chunk
+    // step travels in the scalar offset, which the buffer range check does not cover, so
+    // a chunk past the end could read past the matrix.
+    const int64_t nx = more ? ch + 1 : ch;
+    A.load(nx, an);
+    B.load(nx, bn);
     if (act) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
