@@ -219,8 +219,10 @@ __device__ __forceinline__ Real op_v(const Real* T, const Real* rd, int i, int k
 }
 
 // U_ss^T x = v in place (v in the accumulator layout, the 16 right-hand sides are the
-// columns j = lane % 16): x0 = V^T v, then x = x0 + V^T (v - U_ss^T x0).
-template <typename Real>
+// columns j = lane % 16): x0 = V^T v, then with REFINE x = x0 + V^T (v - U_ss^T x0).
+// The refinement makes the result backward stable whatever cond(U_ss); without it the
+// error grows with cond(U_ss) (a blocked triangular solve with inverted diagonal blocks).
+template <typename Real, bool REFINE>
 __device__ __forceinline__ void solve_fwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int lane) {
   typedef Mfma<Real> M;
   typedef typename M::acc acc;
@@ -235,15 +237,17 @@ __device__ __forceinline__ void solve_fwd(typename Mfma<Real>::acc& v, const Rea
   acc x = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  if constexpr (REFINE) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);      // residual
+    for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);    // residual
 #pragma unroll
-  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+    for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  }
   v = x;
 }
 
-// U_ss x = v in place: x0 = V v, then x = x0 + V (v - U_ss x0).
-template <typename Real>
+// U_ss x = v in place: x0 = V v, then with REFINE x = x0 + V (v - U_ss x0).
+template <typename Real, bool REFINE>
 __device__ __forceinline__ void solve_bwd(typename Mfma<Real>::acc& v, const Real* T, const Real* rd, int lane) {
   typedef Mfma<Real> M;
   typedef typename M::acc acc;
@@ -258,10 +262,12 @@ __device__ __forceinline__ void solve_bwd(typename Mfma<Real>::acc& v, const Rea
   acc x = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  if constexpr (REFINE) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);
+    for (int q = 0; q < 4; ++q) v = M::mac(au[q], x[q], v);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+    for (int q = 0; q < 4; ++q) x = M::mac(av[q], v[q], x);
+  }
   v = x;
 }
 
@@ -486,7 +492,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t 
         const int t = s + 1 + wv;
         acc x;
         get_block(blk(s, t), x);
-        solve_fwd<Real>(x, blk(s, s), s_rd + NB * s, lane);
+        solve_fwd<Real, true>(x, blk(s, s), s_rd + NB * s, lane);
         put_block(blk(s, t), x);
         store(r0, s, r0 + NB * t, x);
       }
@@ -525,7 +531,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrf(Real* __restrict__ ap, int64_t 
           if (s >= nsb) break;
 #pragma unroll
           for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
-          solve_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
+          solve_fwd<Real, true>(S[s], blk(s, s), s_rd + NB * s, lane);
           store(r0, s, cb, S[s]);
         }
       }
@@ -639,7 +645,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
         if (s >= nsb) break;
 #pragma unroll
         for (int t = 0; t < s; ++t) sub_tn<Real>(S[s], blk(t, s), S[t], lane);
-        solve_fwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
+        solve_fwd<Real, false>(S[s], blk(s, s), s_rd + NB * s, lane);
         store(r0, s, S[s]);
       }
     }
@@ -672,7 +678,7 @@ __global__ void __launch_bounds__(NT, 4) k_potrs(const Real* __restrict__ up, in
 #pragma unroll
         for (int t = s + 1; t < NS; ++t)
           if (t < nsb) sub_nn<Real>(S[s], blk(s, t), S[t], lane);
-        solve_bwd<Real>(S[s], blk(s, s), s_rd + NB * s, lane);
+        solve_bwd<Real, false>(S[s], blk(s, s), s_rd + NB * s, lane);
         store(r0, s, S[s]);
       }
     }
