@@ -72,7 +72,7 @@ def check_factor(Up, G, prec, label):
     assert np.all(np.tril(U, -1) == 0)
 
 
-@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 33, 64, 100, 129, 200, 257])
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 33, 64, 100, 129, 200, 257, 1000])
 def test_factor_synthetic(ctx, n):
     say("factor synthetic", n)
     rng = np.random.default_rng(400 + n)
@@ -137,7 +137,8 @@ def test_failure_special_cases(ctx):
     assert list(info) == [condense.cholesky_upper(G)[1] for G in Gs] == [6, 0, 1]
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 1), (17, 16), (33, 21), (64, 40), (130, 7), (130, 70), (300, 19)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 1), (17, 16), (33, 21), (64, 40), (130, 7), (130, 70), (300, 19),
+                                    (1000, 129)])
 def test_solve(ctx, n, nrhs):
     say("solve", n, nrhs)
     rng = np.random.default_rng(440 + n + nrhs)
