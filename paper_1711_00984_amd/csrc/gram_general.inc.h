@@ -118,6 +118,20 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int lpad(int L) { return 4 * ((L + 3) / 4); }   // points padded to whole k-steps
 
+// Workgroups per CU that the LDS layout and the register budget are sized for, where more
+// than the default two paid off (small FP64 orders, whose workgroups are short and spend
+// much of their time in the setup's latency; same-box A/B against two per CU: H1 p = 3
+// 1.12x with four, H1 p = 4, 5 1.10x and 1.07x and H(curl) p = 4 1.06x with three, while
+// H(curl) p = 5 and the FP32 kernels gained nothing or lost, and four spilled at FP64
+// H1 p = 4, 5).  0: the default choice.
+template <int S, int P, typename Real> constexpr int occ_target() {
+  if constexpr (sizeof(Real) != 8) return 0;
+  if constexpr (S == SP_H1 && P == 3) return 4;
+  if constexpr (S == SP_H1 && (P == 4 || P == 5)) return 3;
+  if constexpr (S == SP_HCURL && P == 4) return 3;
+  return 0;
+}
+
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, fully unrolled at compile time
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -220,7 +234,9 @@ template <int S, int P, typename Real> struct Cfg {
         for (int u1 = 1; u1 >= 0; --u1) {
           if (bytes(nb, abuf, u1) > BUDGET) continue;
           // one workgroup per CU leaves no second workgroup to overlap barriers and stalls
-          const double occ = bytes(nb, abuf, u1) * 2 <= BUDGET ? 1.0 : 0.7;
+          double occ = bytes(nb, abuf, u1) * 2 <= BUDGET ? 1.0 : 0.7;
+          constexpr int W = occ_target<S, P, Real>();
+          if (W > 0) occ = bytes(nb, abuf, u1) * W <= BUDGET ? 1.0 : 0.5 * occ;
           const double sc = balance(nb) * occ * (abuf == 2 ? 1.0 : 0.9) * (u1 ? 1.0 : 0.88) * (nb == 1 ? 1.0 : 0.995);
           if (sc > best + 1e-9) { best = sc; pick = nb * 100 + abuf * 10 + u1; }
         }
@@ -882,6 +898,10 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
 template <int S, int P, typename Real> constexpr int min_waves() {
   constexpr int L = npoints(S, P);
   constexpr bool hi = sizeof(Real) == 8 && (S == SP_H1 || S == SP_HCURL) && L <= 10;
+  constexpr int W = occ_target<S, P, Real>();
+  if constexpr (W > 0) {
+    if constexpr (Cfg<S, P, Real>::BYTES * W <= Cfg<S, P, Real>::BUDGET) return W;
+  }
   return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && (L <= DPG_MINW2_LMAX || hi)) ? 2 : 1;
 }
 
