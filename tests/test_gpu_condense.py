@@ -164,6 +164,47 @@ def test_solve(ctx, n, nrhs):
             assert err <= 8 * n * EPS[prec] * kappa, f"n={n} nrhs={nrhs} {prec} e={e}: {err:.3e}"
 
 
+def test_factor_without_info_matches(ctx):
+    """info is optional: the factor written without it is bit for bit the one written with it."""
+    n = 200
+    rng = np.random.default_rng(460)
+    Gs = np.stack([spd(n, rng) for _ in range(2)])
+    ap = np.concatenate([og.packed_upper(G) for G in Gs])
+    for prec in ("fp64", "fp32"):
+        t1 = torch.from_numpy(ap).to(DT[prec]).cuda()
+        t2 = t1.clone()
+        info = torch.full((2,), -99, dtype=torch.int32, device="cuda")
+        ctx.cholesky(t1, n, info=info)
+        ctx.cholesky(t2, n)
+        torch.cuda.synchronize()
+        assert list(info.cpu().numpy()) == [0, 0]
+        assert torch.equal(t1, t2), prec
+
+
+def test_solve_many_rhs_blocks(ctx):
+    """Right-hand sides over several 64-column workgroups, the last one partial, against the
+    oracle's solve and against solving the columns one block at a time."""
+    n, nrhs = 200, 150
+    rng = np.random.default_rng(470)
+    G = spd(n, rng)
+    up = condense.cholesky_packed(og.packed_upper(G), n)[0]
+    B = rng.standard_normal((1, nrhs, n))
+    tu = torch.from_numpy(up).cuda()
+    tb = torch.from_numpy(B).cuda()
+    ctx.cholesky_solve(tu, n, tb)
+    parts = [torch.from_numpy(np.ascontiguousarray(B[:, c:c + 37])).cuda() for c in range(0, nrhs, 37)]
+    for t in parts:
+        ctx.cholesky_solve(tu, n, t)
+    torch.cuda.synchronize()
+    X = tb.cpu().numpy()[0]
+    R = condense.solve_packed(up, n, B[0].T)
+    err = np.abs(X.T - R).max() / np.abs(R).max()
+    assert err <= 8 * n * EPS["fp64"] * np.linalg.cond(G), err
+    # each column's result does not depend on which workgroup solved it
+    Y = np.concatenate([t.cpu().numpy()[0] for t in parts], axis=0)
+    assert np.abs(Y - X).max() <= 8 * n * EPS["fp64"] * np.linalg.cond(G) * np.abs(X).max()
+
+
 def test_condensation_round_trip(ctx, dpg):
     """Factor H(div) p=3 Grams where they were integrated, solve G X = B with
     them, and check G X = B with the Grams recomputed."""
