@@ -124,6 +124,14 @@ constexpr int lpad(int L) { return 4 * ((L + 3) / 4); }   // points padded to wh
 // 1.12x with four, H1 p = 4, 5 1.10x and 1.07x and H(curl) p = 4 1.06x with three, while
 // H(curl) p = 5 and the FP32 kernels gained nothing or lost, and four spilled at FP64
 // H1 p = 4, 5).  0: the default choice.
+// Stage-1 MFMAs of the next step issued before the stores of the current one (DPG_PIPE
+// for all).  Measured per space and order (FP64, p = 6..10, same-box A/B over three
+// rounds): only H(div) p = 10 gained (1.055x); H1 p = 9 lost 3.5 %, the others moved
+// within 1 %.
+template <int S, int P, typename Real> constexpr bool pipe_steps() {
+  return DPG_PIPE || (sizeof(Real) == 8 && S == SP_HDIV && P == 10);
+}
+
 template <int S, int P, typename Real> constexpr int occ_target() {
   if constexpr (sizeof(Real) != 8) return 0;
   if constexpr (S == SP_H1 && P == 3) return 4;
@@ -652,10 +660,10 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
         }
       }
     };
-    // steps (pi, yc) in order; with DPG_PIPE the MFMAs of the next step are issued before the
-    // stores of the current one, so the stores wait on finished accumulators only
+    // steps (pi, yc) in order; pipelined (pipe_steps), the MFMAs of the next step are issued
+    // before the stores of the current one, so the stores wait on finished accumulators only
     constexpr int NSTEP = NP * YCH;
-    if constexpr (DPG_PIPE) {
+    if constexpr (pipe_steps<S, P, Real>()) {
       Acc ping[YB], pong[YB];
       mm(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, ping);
       static_for<NSTEP>([&](auto STEP) {
