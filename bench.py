@@ -353,10 +353,12 @@ def run_extra(ctx, dpg, stream, E, X, out64):
                                  "hbm_frac": round(moved / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     log(f"[bench] extra replicate {res['replicate_h1_p7_x3']}")
     del src, dst
-    # non-uniform orders (p1, p2, p3): one rule per coordinate, least order outermost; the same
-    # elements at (7, 7, 7) through the uniform kernel for comparison
+    # non-uniform orders (p1, p2, p3), one rule per coordinate: the route the entry point takes
+    # (orders embedded in the uniform kernel of order max p_d) and the per-direction kernel
+    # (least order outermost); (7, 7, 7) also through the uniform kernel for comparison
     ani = []
-    for space, q in (("H1", (7, 6, 5)), ("H1", (7, 7, 7)), ("HCURL", (6, 5, 4)), ("HDIV", (5, 6, 4))):
+    for space, q in (("H1", (7, 6, 5)), ("H1", (7, 7, 7)), ("HCURL", (6, 5, 4)), ("HDIV", (5, 6, 4)),
+                     ("L2", (8, 7, 6))):
         nd = dpg.gram_dim_aniso(space, q)
         mm = nd * (nd + 1) // 2
         n_a = int(min(4096, (2 << 30) // (mm * 8)))
@@ -367,9 +369,14 @@ def run_extra(ctx, dpg, stream, E, X, out64):
         w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, nq=nqa if len(set(q)) == 1 else 0,
                                                      stream=stream), 3, 1, stream)
         kk = float(np.mean(pr))
-        row = {"space": space, "p": list(q), "n_elem": n_a, "kernel_ms": round(kk, 3),
+        route = ctx.aniso_route(space, q, nq=nqa if len(set(q)) == 1 else 0)
+        row = {"space": space, "p": list(q), "n_elem": n_a, "route": route, "kernel_ms": round(kk, 3),
                "elements_per_s": round(n_a / (kk * 1e-3), 1),
                "hbm_gbs": round(mm * 8 * n_a / (kk * 1e-3) / 1e9, 1)}
+        if route == "embedded":
+            w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, path="general", stream=stream),
+                                  3, 1, stream)
+            row["per_direction_ms"] = round(float(np.mean(pr)), 3)
         if len(set(q)) == 1:
             w, pr = time_launches(lambda: ctx.gram(space, q[0], Xa, out=o, stream=stream), 3, 1, stream)
             row["uniform_kernel_ms"] = round(float(np.mean(pr)), 3)

@@ -199,14 +199,29 @@ int64_t dpg_noalloc_max_elements(void);
  * L2 p_d; H(div) p_d+1 if d = a else p_d; H(curl) p_d if d = a else p_d+1,
  * flat index as for uniform orders (i1 fastest, components in order).  Each
  * coordinate takes its own Gauss rule (p_d + 1 points, p_d for L2), or opts->nq
- * points in every direction when nq > 0 (at most 11); the direction of least
- * order is contracted last, in the outermost loop (equal orders with nq = 0 take the
- * uniform kernels of dpg_gram_integrate's quadrature path, which compute the same
- * sums).  Output, geometry, status,
+ * points in every direction when nq > 0 (at most 11).  Kernels, by opts->path:
+ *   DPG_PATH_AUTO: with the default rule (nq = 0), equal orders take the uniform
+ *     kernels of dpg_gram_integrate's quadrature path; other orders, where order
+ *     P = max p_d carries at most about four times the entries needed, the uniform
+ *     kernels of order P with each direction on its own rule (zero-weight points
+ *     pad it to order P's count) into a scratch buffer, from which the submatrix
+ *     is copied out (the 1D bases are hierarchical, Sections 2.4 and 2.8.2).  The
+ *     scratch is held by the context (a stream-ordered pool that keeps its memory;
+ *     at most 4 GiB per call, batches above run in chunks).  Everything else takes
+ *     the per-direction kernel;
+ *   DPG_PATH_GENERAL: always the per-direction kernel, which contracts the
+ *     direction of least order last, in the outermost loop.
+ * All routes compute the same sums (rounding aside).  Output, geometry, status,
  * weights and precision as for dpg_gram_integrate, with packed length
- * n (n+1)/2, n = dpg_gram_dim_aniso(space, p).  Quadrature path only
- * (DPG_PATH_REDUCED is rejected).  Errors: DPG_EINVAL, DPG_ENOTINIT, DPG_EHIP. */
+ * n (n+1)/2, n = dpg_gram_dim_aniso(space, p).  DPG_PATH_REDUCED is rejected.
+ * Errors: DPG_EINVAL, DPG_ENOTINIT, DPG_EHIP. */
 int64_t dpg_gram_dim_aniso(int space, const int32_t* p);
+/* The kernels dpg_gram_integrate_aniso takes for (space, p, opts) (host only, no
+ * device work): DPG_ROUTE_UNIFORM, DPG_ROUTE_EMBEDDED or DPG_ROUTE_PER_DIRECTION
+ * (the three routes above); DPG_EINVAL for bad space/orders, DPG_ENOTINIT for a
+ * null context. */
+enum { DPG_ROUTE_PER_DIRECTION = 0, DPG_ROUTE_UNIFORM = 1, DPG_ROUTE_EMBEDDED = 2 };
+int dpg_aniso_route(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts* opts);
 int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                              const dpg_opts* opts, void* stream);
 

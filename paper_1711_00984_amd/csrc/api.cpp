@@ -104,7 +104,29 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
 dpg_ctx::~dpg_ctx() {
   dpg::destroy_plans(this);
   if (d_tab64) (void)hipFree(d_tab64);
+  if (pool) (void)hipMemPoolDestroy(pool);
 }
+
+namespace dpg {
+
+hipMemPool_t ctx_scratch_pool(const dpg_ctx* ctx) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (!ctx->pool) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = ctx->device;
+    hipMemPool_t pl = nullptr;
+    if (hipMemPoolCreate(&pl, &props) != hipSuccess) return nullptr;
+    uint64_t keep = UINT64_MAX;   // keep the memory between calls
+    (void)hipMemPoolSetAttribute(pl, hipMemPoolAttrReleaseThreshold, &keep);
+    ctx->pool = pl;
+  }
+  return ctx->pool;
+}
+
+}  // namespace dpg
 
 using dpg::fail;
 using dpg::hip_fail;
@@ -317,6 +339,20 @@ int64_t dpg_gram_dim_aniso(int space, const int32_t* p) {
   return n;
 }
 
+static int aniso_route(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts& o) {
+  if (p[0] == p[1] && p[1] == p[2] && o.nq == 0 && o.path == DPG_PATH_AUTO && p[0] <= ctx->p_max)
+    return DPG_ROUTE_UNIFORM;
+  return dpg::embed_applies(ctx, space, p, o) ? DPG_ROUTE_EMBEDDED : DPG_ROUTE_PER_DIRECTION;
+}
+
+int dpg_aniso_route(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts* opts) {
+  if (!ctx) return fail(DPG_ENOTINIT, "context is NULL");
+  dpg_opts o;
+  if (opts) o = *opts; else dpg_opts_default(&o);
+  if (dpg_gram_dim_aniso(space, p) < 0) return fail(DPG_EINVAL, "invalid space or orders");
+  return aniso_route(ctx, space, p, o);
+}
+
 int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                              const dpg_opts* opts, void* stream) {
   dpg_opts o;
@@ -331,7 +367,8 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
   if (o.path == DPG_PATH_REDUCED) return fail(DPG_EINVAL, "non-uniform orders use the quadrature path only");
   if (o.nq < 0 || o.nq > dpg::ANISO_LMAX) return fail(DPG_EINVAL, "nq=%d outside [0, %d]", o.nq, dpg::ANISO_LMAX);
   if (geom->n_elem == 0) return DPG_OK;
-  if (p[0] == p[1] && p[1] == p[2] && o.nq == 0 && p[0] <= ctx->p_max) {
+  const int route = aniso_route(ctx, space, p, o);
+  if (route == DPG_ROUTE_UNIFORM) {
     // equal orders with the default rule: the uniform quadrature kernels compute the same sums
     dpg_opts u = o;
     u.path = DPG_PATH_GENERAL;
@@ -339,6 +376,8 @@ int dpg_gram_integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, co
     return dpg::launch_elements(ctx, space, p[0], geom, out, u, nullptr, geom->n_elem, nullptr, g,
                                 static_cast<hipStream_t>(stream));
   }
+  if (route == DPG_ROUTE_EMBEDDED)
+    return dpg::integrate_aniso_embed(ctx, space, p, geom, out, o, static_cast<hipStream_t>(stream));
   return dpg::integrate_aniso(ctx, space, p, geom, out, o, static_cast<hipStream_t>(stream));
 }
 

@@ -62,6 +62,7 @@ struct dpg_ctx {
   mutable std::mutex mu;                                    // guards tune and plans
   mutable std::map<dpg::TuneKey, dpg::TuneVal> tune;
   mutable std::vector<std::shared_ptr<dpg::BatchPlan>> plans;   // most recent last
+  mutable hipMemPool_t pool = nullptr;                      // stream-ordered scratch (created on first use)
   ~dpg_ctx();
 };
 
@@ -84,6 +85,17 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
 // generic kernel: one rule per direction (opts nq points in every direction when nq > 0).
 int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                     const dpg_opts& o, hipStream_t st);
+
+// Non-uniform orders on the uniform kernels of order max p_d (aniso_embed.hip): whether
+// the call takes that route (default rule, AUTO path, orders <= 10, and at most about
+// four times the entries needed), and the launch.
+bool embed_applies(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts& o);
+int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
+                          const dpg_opts& o, hipStream_t st);
+
+// The context's scratch pool on its device (memory kept between calls), created on first
+// use; nullptr if the device has none.
+hipMemPool_t ctx_scratch_pool(const dpg_ctx* ctx);
 
 // Load the tuning table shipped with the library (dpg_tables_build).
 int load_default_tune(dpg_ctx* ctx);

@@ -118,12 +118,6 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int lpad(int L) { return 4 * ((L + 3) / 4); }   // points padded to whole k-steps
 
-// Workgroups per CU that the LDS layout and the register budget are sized for, where more
-// than the default two paid off (small FP64 orders, whose workgroups are short and spend
-// much of their time in the setup's latency; same-box A/B against two per CU: H1 p = 3
-// 1.12x with four, H1 p = 4, 5 1.10x and 1.07x and H(curl) p = 4 1.06x with three, while
-// H(curl) p = 5 and the FP32 kernels gained nothing or lost, and four spilled at FP64
-// H1 p = 4, 5).  0: the default choice.
 // Stage-1 MFMAs of the next step issued before the stores of the current one (DPG_PIPE
 // for all).  Measured per space and order (FP64, p = 6..10, same-box A/B over three
 // rounds): only H(div) p = 10 gained (1.055x); H1 p = 9 lost 3.5 %, the others moved
@@ -132,6 +126,12 @@ template <int S, int P, typename Real> constexpr bool pipe_steps() {
   return DPG_PIPE || (sizeof(Real) == 8 && S == SP_HDIV && P == 10);
 }
 
+// Workgroups per CU that the LDS layout and the register budget are sized for, where more
+// than the default two paid off (small FP64 orders, whose workgroups are short and spend
+// much of their time in the setup's latency; same-box A/B against two per CU: H1 p = 3
+// 1.12x with four, H1 p = 4, 5 1.10x and 1.07x and H(curl) p = 4 1.06x with three, while
+// H(curl) p = 5 and the FP32 kernels gained nothing or lost, and four spilled at FP64
+// H1 p = 4, 5).  0: the default choice.
 template <int S, int P, typename Real> constexpr int occ_target() {
   if constexpr (sizeof(Real) != 8) return 0;
   if constexpr (S == SP_H1 && P == 3) return 4;
@@ -258,6 +258,8 @@ template <int S, int P, typename Real> struct Cfg {
   static constexpr int BYTES = bytes(NB, ABUF, U1TAB);
 };
 
+// T, z, w: the 1D tables and points of direction 1; T2/T3, z2/z3, w2/w3 those of
+// directions 2 and 3 (the same arrays when every direction takes one rule)
 struct SmemPtrs {
   void* fld;
   void* A;
@@ -269,6 +271,12 @@ struct SmemPtrs {
   double* X;
   unsigned char* xd;
   int* bad;
+  void* T2;
+  void* T3;
+  double* z2;
+  double* z3;
+  double* w2;
+  double* w3;
 };
 // (i2, j2) of x slot s: all pairs (i2 fastest) or the triangle i2 <= j2
 template <int R2a, bool DIAG>
@@ -410,7 +418,7 @@ __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real
   using R3 = S3Roles<S, P, Real, A, B>;
   using M = Mma<Real>;
   constexpr int L = Sh::L, L2 = L * L, KTL = KT * L, QS = R3::QS, W3 = R3::W3;
-  const Real* sT = static_cast<const Real*>(sm.T);
+  const Real* sT = static_cast<const Real*>(sm.T3);   // direction 3
   const Real* sF = static_cast<const Real*>(sm.fld);
 #pragma unroll
   for (int rd = 0; rd < R3::ROUNDS; ++rd) {
@@ -467,7 +475,8 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   constexpr int NXv = DIAG ? BC::NXD : BC::NX;
   constexpr bool C2 = Cache2<S, P, Real, A, B>::ON && !DIAG;
   constexpr int YB = imin(DPG_YB, BC::NYM), YCH = (BC::NYM + YB - 1) / YB;
-  const Real* sT = static_cast<const Real*>(sm.T);
+  const Real* sT = static_cast<const Real*>(sm.T);     // direction 1 (stage 1)
+  const Real* sT2 = static_cast<const Real*>(sm.T2);   // direction 2 (stage 2)
   const Real* sU1 = static_cast<const Real*>(sm.U1);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -502,7 +511,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
         const Real a = Ab[(q * LP + 4 * ks) * 16];
         Real u;
         if constexpr (C2) u = rg.u2[q * RPP + ks];
-        else u = sT[r2 * KTL + ia + 4 * ks] * sT[s2 * KTL + jb + 4 * ks];
+        else u = sT2[r2 * KTL + ia + 4 * ks] * sT2[s2 * KTL + jb + 4 * ks];
         acc2[g] = M::mac(a, u, acc2[g]);
       });
     });
@@ -736,7 +745,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   }
 }
 
-template <int S, int P, typename Real, int A, int B>
+// EMB: the points of direction d past ga.emb_L[d] carry zero weight (their fields are zero
+// and their Jacobian is not checked)
+template <int S, int P, typename Real, int A, int B, bool EMB>
 __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs sm, int j3_lo, int j3_hi,
                                           Real* __restrict__ outp) {
   using Sh = Shape<S, P>;
@@ -747,6 +758,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   constexpr int L = Sh::L, L2 = L * L, L3 = L2 * L, KTL = KT * L, RPP = BC::RPP;
   Real* sF = static_cast<Real*>(sm.fld);
   const Real* sT = static_cast<const Real*>(sm.T);
+  const Real* sT2 = static_cast<const Real*>(sm.T2);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -754,12 +766,21 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   // ---------------- metric -> coefficient fields, layout [f][n][m][l] ----------------
   for (int pt = tid; pt < L3; pt += NTHREADS) {
     const int l = pt % L, m = (pt / L) % L, n = pt / L2;
+    if constexpr (EMB) {
+      if (l >= ga.emb_L[0] || m >= ga.emb_L[1] || n >= ga.emb_L[2]) {
+        static_for<BC::PL.nf>([&](auto F) {
+          constexpr int f = decltype(F)::value;
+          sF[(f * L + n) * L2 + m * L + l] = Real(0);
+        });
+        continue;
+      }
+    }
     double J[3][3], adj[3][3];
-    jacobian_at(ga.geom_kind, sm.X, sm.z[l], sm.z[m], sm.z[n], J);
+    jacobian_at(ga.geom_kind, sm.X, sm.z[l], sm.z2[m], sm.z3[n], J);
     const double det = adjugate(J, adj);
     if (!(det > 0.0)) *sm.bad = 1;
     const double idet = 1.0 / det;
-    const double wq = sm.w[l] * sm.w[m] * sm.w[n];
+    const double wq = sm.w[l] * sm.w2[m] * sm.w3[n];
     const double wv = wq * ga.w0, wd = wq * ga.w1;
     static_for<BC::PL.nf>([&](auto F) {
       constexpr int f = decltype(F)::value;
@@ -821,7 +842,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       constexpr int q = decltype(Q)::value;
       static_for<RPP>([&](auto KS) {
         constexpr int ks = decltype(KS)::value;
-        rg.u2[q * RPP + ks] = sT[BC::PL.qr2[q] * KTL + ia + 4 * ks] * sT[BC::PL.qs2[q] * KTL + jb + 4 * ks];
+        rg.u2[q * RPP + ks] = sT2[BC::PL.qr2[q] * KTL + ia + 4 * ks] * sT2[BC::PL.qs2[q] * KTL + jb + 4 * ks];
       });
     });
   }
@@ -913,17 +934,27 @@ template <int S, int P, typename Real> constexpr int min_waves() {
   return (Cfg<S, P, Real>::BYTES * 2 <= Cfg<S, P, Real>::BUDGET && (L <= DPG_MINW2_LMAX || hi)) ? 2 : 1;
 }
 
-template <int S, int P, typename Real, bool LISTED>
-__global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general(GeneralArgs ga) {
+// Per-direction rules (EMB): one table and point set per direction, each of a rule
+// of emb_L[d] <= L points padded with zero-weight points to L.
+template <typename Real, bool EMB> constexpr int n_dir_tables() { return EMB ? 3 : 1; }
+
+// Body of the general-path kernels.  EMB: the orders (p1, p2, p3) <= P embedded in
+// order P (the functions of order p_d in direction d are the first ones of order P: the
+// 1D bases are hierarchical, Sections 2.4 and 2.8.2), each direction with its own rule,
+// and only the column
+// slabs j3 < emb_jmax[b] of component b; the output keeps order P's numbering.
+template <int S, int P, typename Real, bool LISTED, bool EMB>
+__device__ __forceinline__ void general_body(const GeneralArgs& ga) {
   using Sh = Shape<S, P>;
   using CF = Cfg<S, P, Real>;
   constexpr int L = Sh::L;
+  constexpr int ND = n_dir_tables<Real, EMB>();
   __shared__ Real s_fld[CF::FLD_LEN];
   __shared__ Real s_A[CF::ABUF * CF::NB * CF::AONE];
   __shared__ Real s_U1[CF::U1TAB ? CF::U1_LEN : 1];
-  __shared__ Real s_T[CF::T_LEN];
+  __shared__ Real s_T[ND * CF::T_LEN];
   __shared__ Real s_hd[CF::HD ? CF::HD_LEN : 1];
-  __shared__ double s_z[L], s_w[L], s_X[24];
+  __shared__ double s_z[ND * L], s_w[ND * L], s_X[24];
   __shared__ unsigned char s_xd[2 * 80];
   __shared__ int s_bad;
 
@@ -937,11 +968,31 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
     const int64_t e = ids ? int64_t(ids[item]) : item;
     const int s_lo = grp * G, s_hi = imin(Sh::NSLAB, s_lo + G);
 
-    const Real* tR = static_cast<const Real*>(ga.tabR);
-    for (int i = tid; i < CF::T_LEN; i += NTHREADS) s_T[i] = i < 2 * KT * L ? tR[2 * L + i] : Real(0);
+    if constexpr (EMB) {
+      // direction d: its rule's tables with stride L, zero past its emb_L[d] points; the
+      // padding points sit at the centre with weight zero
+      static_for<3>([&](auto D) {
+        constexpr int d = decltype(D)::value;
+        const int Ld = ga.emb_L[d];
+        const Real* tR = static_cast<const Real*>(ga.emb_tabR[d]);
+        for (int i = tid; i < CF::T_LEN; i += NTHREADS) {
+          const int l = i % L, f = i / L;
+          s_T[d * CF::T_LEN + i] = i < 2 * KT * L && l < Ld ? tR[2 * Ld + f * Ld + l] : Real(0);
+        }
+        if (tid < L) {
+          s_z[d * L + tid] = tid < Ld ? ga.emb_tab64[d][tid] : 0.5;
+          s_w[d * L + tid] = tid < Ld ? ga.emb_tab64[d][Ld + tid] : 0.0;
+        }
+      });
+    } else {
+      const Real* tR = static_cast<const Real*>(ga.tabR);
+      for (int i = tid; i < CF::T_LEN; i += NTHREADS) s_T[i] = i < 2 * KT * L ? tR[2 * L + i] : Real(0);
+    }
     // stage-3 output buffers: the padding rows (m >= L) and columns (l >= L) stay zero
     for (int i = tid; i < CF::ABUF * CF::NB * CF::AONE; i += NTHREADS) s_A[i] = Real(0);
-    if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
+    if constexpr (!EMB) {
+      if (tid < L) { s_z[tid] = ga.tab64[tid]; s_w[tid] = ga.tab64[L + tid]; }
+    }
     const int ng = geom_stride(ga.geom_kind);
     if (tid < ng) s_X[tid] = ga.geom[e * ng + tid];
     if (tid < 80) {
@@ -954,7 +1005,9 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
     if (tid == 0) s_bad = 0;
     __syncthreads();
 
-    SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_hd, s_z, s_w, s_X, s_xd, &s_bad};
+    constexpr int D2 = EMB ? 1 : 0, D3 = EMB ? 2 : 0;
+    SmemPtrs sm{s_fld, s_A, s_U1, s_T, s_hd, s_z, s_w, s_X, s_xd, &s_bad,
+                s_T + D2 * CF::T_LEN, s_T + D3 * CF::T_LEN, s_z + D2 * L, s_z + D3 * L, s_w + D2 * L, s_w + D3 * L};
     Real* outp = static_cast<Real*>(ga.out) + (ga.out_offset ? ga.out_offset[e] : e * ga.packed_len);
     // component b owns slabs [slab0(b), slab0(b) + R3(b)); visit the blocks (a, b), a <= b,
     // for the j3 range of every component the slab group touches
@@ -962,19 +1015,20 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
     auto jr = [&](int b, int& lo, int& hi) {
       lo = imax(s_lo, Sh::slab0(b)) - Sh::slab0(b);
       hi = imin(s_hi, Sh::slab0(b) + Sh::R(b, 2)) - Sh::slab0(b);
+      if constexpr (EMB) hi = imin(hi, ga.emb_jmax[b]);
       return lo < hi;
     };
     int lo, hi;
-    if (jr(0, lo, hi)) bad = run_block<S, P, Real, 0, 0>(ga, sm, lo, hi, outp);
+    if (jr(0, lo, hi)) bad = run_block<S, P, Real, 0, 0, EMB>(ga, sm, lo, hi, outp);
     if constexpr (Sh::NC == 3) {
       if (!bad && jr(1, lo, hi)) {
-        bad = run_block<S, P, Real, 0, 1>(ga, sm, lo, hi, outp);
-        if (!bad) bad = run_block<S, P, Real, 1, 1>(ga, sm, lo, hi, outp);
+        bad = run_block<S, P, Real, 0, 1, EMB>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 1, 1, EMB>(ga, sm, lo, hi, outp);
       }
       if (!bad && jr(2, lo, hi)) {
-        bad = run_block<S, P, Real, 0, 2>(ga, sm, lo, hi, outp);
-        if (!bad) bad = run_block<S, P, Real, 1, 2>(ga, sm, lo, hi, outp);
-        if (!bad) bad = run_block<S, P, Real, 2, 2>(ga, sm, lo, hi, outp);
+        bad = run_block<S, P, Real, 0, 2, EMB>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 1, 2, EMB>(ga, sm, lo, hi, outp);
+        if (!bad) bad = run_block<S, P, Real, 2, 2, EMB>(ga, sm, lo, hi, outp);
       }
     }
     if (bad) {
@@ -1008,6 +1062,24 @@ __global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general
   } else {
     run(blockIdx.x, ga.n_items, ga.elem_ids);   // one workgroup per (item, slab group)
   }
+}
+
+template <int S, int P, typename Real, bool LISTED>
+__global__ void __launch_bounds__(NTHREADS, (min_waves<S, P, Real>())) k_general(GeneralArgs ga) {
+  general_body<S, P, Real, LISTED, false>(ga);
+}
+
+// Workgroups per CU for the per-direction-rule kernel: the uniform kernel's choice where
+// its two extra tables still fit beside them, at most three (four spilled at H1 p = 3).
+template <int S, int P, typename Real> constexpr int min_waves_emb() {
+  constexpr int W = imin(3, min_waves<S, P, Real>());
+  constexpr int XB = 2 * Cfg<S, P, Real>::T_LEN * int(sizeof(Real)) + 4 * npoints(S, P) * 8;
+  return (Cfg<S, P, Real>::BYTES + XB) * W <= Cfg<S, P, Real>::BUDGET ? W : (W > 1 ? W - 1 : 1);
+}
+
+template <int S, int P, typename Real>
+__global__ void __launch_bounds__(NTHREADS, (min_waves_emb<S, P, Real>())) k_embed(GeneralArgs ga) {
+  general_body<S, P, Real, false, true>(ga);
 }
 
 // One (space, p, precision): a plain launch (split into launches under the
@@ -1049,6 +1121,45 @@ hipError_t dispatch_general_p(int p, const GeneralArgs& a, hipStream_t st) {
     case 11: return launch_general_one<S, 11, Real, LISTED>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Per-direction rules embedded in order P: plain launches of k_embed (orders up to 10).
+template <int S, int P, typename Real>
+hipError_t launch_embed_one(const GeneralArgs& a, hipStream_t st) {
+  constexpr int NS = Shape<S, P>::NSLAB;
+  GeneralArgs c = a;
+  c.slab_group = slab_group_for(NS, a.n_items, a.slab_group);
+  if (c.diag_inline < 0 || !diag_inline_ok(S, P)) c.diag_inline = diag_inline_ok(S, P) ? 1 : 0;
+  const int ngroups = (NS + c.slab_group - 1) / c.slab_group;
+  const int64_t max_items = launch_items(ngroups);
+  for (int64_t base = 0; base < a.n_items; base += max_items) {
+    c.item_base = a.item_base + base;
+    c.n_items = (a.n_items - base) < max_items ? (a.n_items - base) : max_items;
+    hipLaunchKernelGGL((k_embed<S, P, Real>), dim3(unsigned(c.n_items * ngroups)), dim3(NTHREADS), 0, st, c);
+  }
+  return hipGetLastError();
+}
+
+template <int S, typename Real>
+hipError_t dispatch_embed_p(int p, const GeneralArgs& a, hipStream_t st) {
+  switch (p) {
+    case 1: return launch_embed_one<S, 1, Real>(a, st);
+    case 2: return launch_embed_one<S, 2, Real>(a, st);
+    case 3: return launch_embed_one<S, 3, Real>(a, st);
+    case 4: return launch_embed_one<S, 4, Real>(a, st);
+    case 5: return launch_embed_one<S, 5, Real>(a, st);
+    case 6: return launch_embed_one<S, 6, Real>(a, st);
+    case 7: return launch_embed_one<S, 7, Real>(a, st);
+    case 8: return launch_embed_one<S, 8, Real>(a, st);
+    case 9: return launch_embed_one<S, 9, Real>(a, st);
+    case 10: return launch_embed_one<S, 10, Real>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int S>
+hipError_t dispatch_embed(int p, int prec, const GeneralArgs& a, hipStream_t st) {
+  return prec ? dispatch_embed_p<S, float>(p, a, st) : dispatch_embed_p<S, double>(p, a, st);
 }
 
 // Plain launches (LISTED = false) and listed ones are instantiated in separate files,

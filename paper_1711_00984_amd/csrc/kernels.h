@@ -43,6 +43,13 @@ struct GeneralArgs {
                              // triangular x tiling, 1 each closing its slab (full x tiling)
   const int32_t* list;       // listed launch: {item count, first entry in elem_ids} in device
                              // memory (nullptr: n_items and elem_ids as given)
+  // Per-direction rules embedded in the order of the launch (launch_embed_*): direction d
+  // takes the emb_L[d]-point rule (table blocks emb_tab64[d], emb_tabR[d]), and component b
+  // only its column slabs j3 < emb_jmax[b].
+  const double* emb_tab64[3];
+  const void* emb_tabR[3];
+  int emb_L[3];
+  int emb_jmax[3];
 };
 
 // Workgroups of a listed launch (the item count is on the device): enough to fill the
@@ -74,6 +81,13 @@ hipError_t launch_general_list_h1(int p, int prec, const GeneralArgs& a, hipStre
 hipError_t launch_general_list_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_general_list_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_general_list_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
+
+// General path with per-direction rules embedded in order p (GeneralArgs::emb_*): the
+// output has order p's numbering.
+hipError_t launch_embed_h1(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_embed_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_embed_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
+hipError_t launch_embed_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
 
 // Reduced (constant Jacobian, exact 1D integrals) path; affine geometry only.
 hipError_t launch_affine(int space, int p, int prec, const GeneralArgs& a, hipStream_t s);

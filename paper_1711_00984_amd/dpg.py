@@ -110,6 +110,8 @@ _lib.dpg_replicate_blocks.argtypes = [_vp, _i64, _i64, _i, _vp, _vp, _i, _vp]
 _lib.dpg_replicate_blocks.restype = _i
 _lib.dpg_gram_dim_aniso.argtypes = [_i, _vp]
 _lib.dpg_gram_dim_aniso.restype = _i64
+_lib.dpg_aniso_route.argtypes = [_vp, _i, _vp, _vp]
+_lib.dpg_aniso_route.restype = _i
 _lib.dpg_gram_integrate_aniso.argtypes = [_vp, _i, _vp, ctypes.POINTER(Geometry), _vp, ctypes.POINTER(Opts), _vp]
 _lib.dpg_gram_integrate_aniso.restype = _i
 _lib.dpg_cholesky_packed.argtypes = [_vp, _i64, _i64, _vp, _vp, _i, _vp]
@@ -369,9 +371,17 @@ class Context:
                                          _stream_ptr(stream)))
         return out
 
+    def aniso_route(self, space, p, prec="fp64", nq=0, path="auto"):
+        """Kernels dpg_gram_integrate_aniso takes: "uniform", "embedded" or "per-direction"."""
+        o = _opts(prec, path, nq, 1.0, 1.0, None)
+        r = _lib.dpg_aniso_route(self._h, space_id(space), _orders(p), ctypes.byref(o))
+        _check(min(r, 0))
+        return {0: "per-direction", 1: "uniform", 2: "embedded"}[r]
+
     def gram_aniso(self, space, p, geom, kind="trilinear", out=None, prec="fp64", nq=0, w0=1.0, w1=1.0,
-                   status=None, stream=None):
-        """Packed Grams of non-uniform orders p = (p1, p2, p3) (dpg_gram_integrate_aniso)."""
+                   status=None, stream=None, path="auto"):
+        """Packed Grams of non-uniform orders p = (p1, p2, p3) (dpg_gram_integrate_aniso);
+        path "general" forces the per-direction kernel."""
         g = _geometry(geom, kind)
         dt = torch.float64 if prec in ("fp64", FP64) else torch.float32
         nd = gram_dim_aniso(space, p)
@@ -382,7 +392,7 @@ class Context:
             out = torch.empty(n, dtype=dt, device=geom.device)
         elif out.dtype != dt or out.numel() < n or not out.is_contiguous():
             raise ValueError("out has the wrong dtype or size")
-        o = _opts(prec, "auto", nq, w0, w1, status)
+        o = _opts(prec, path, nq, w0, w1, status)
         _check(_lib.dpg_gram_integrate_aniso(self._h, space_id(space), _orders(p), ctypes.byref(g),
                                              out.data_ptr(), ctypes.byref(o), _stream_ptr(stream)))
         return out

@@ -38,9 +38,9 @@ def ctx(dpg):
     c.close()
 
 
-def run(ctx, space, q, geom, kind="trilinear", prec="fp64", nq=0, status=None):
+def run(ctx, space, q, geom, kind="trilinear", prec="fp64", nq=0, status=None, path="auto"):
     g = torch.from_numpy(np.ascontiguousarray(geom)).cuda()
-    out = ctx.gram_aniso(space, q, g, kind=kind, prec=prec, nq=nq, status=status)
+    out = ctx.gram_aniso(space, q, g, kind=kind, prec=prec, nq=nq, status=status, path=path)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -112,6 +112,81 @@ def test_uniform_orders_match_the_uniform_kernels(ctx, space, p):
         assert fro <= TOL64 and mx <= TOL64, f"{space} p={p} e={e}"
 
 
+EMBEDDED = [("H1", (7, 6, 5)), ("H1", (3, 1, 2)), ("H1", (10, 9, 8)), ("HCURL", (6, 5, 4)), ("HCURL", (2, 3, 1)),
+            ("HDIV", (5, 6, 4)), ("HDIV", (4, 4, 2)), ("L2", (8, 7, 6)), ("L2", (3, 2, 1))]
+
+
+@pytest.mark.parametrize("space,q", EMBEDDED)
+def test_embedded_route(ctx, space, q):
+    """Orders embedded in the uniform kernel of order max p_d (each direction on its
+    own rule, padded with zero-weight points; the submatrix copied out of a scratch
+    buffer) against the oracle and against the per-direction kernel, FP64 and FP32."""
+    say("embedded", space, q)
+    assert ctx.aniso_route(space, q) == "embedded"
+    assert ctx.aniso_route(space, q, path="general") == "per-direction"
+    assert ctx.aniso_route(space, q, nq=5) == "per-direction"
+    n = shapes.dimension(space, q)
+    E = 3 if n <= 400 else 2
+    X = meshgen.perturbed_hexes(E, seed=700 + sum(q))
+    a = run(ctx, space, q, X)
+    g = run(ctx, space, q, X, path="general")
+    a32 = run(ctx, space, q, X, prec="fp32")
+    for e in range(E):
+        R = og.gram(space, q, "trilinear", X[e])
+        fro, mx = rel(elem(a, e, space, q), R)
+        assert fro <= TOL64 and mx <= TOL64, f"{space} {q} e={e}: fro {fro:.3e} max {mx:.3e}"
+        fro, mx = rel(elem(a, e, space, q), elem(g, e, space, q))
+        assert fro <= TOL64 and mx <= TOL64, f"{space} {q} e={e} vs per-direction: {fro:.3e} {mx:.3e}"
+        fro32, _ = rel(elem(a32, e, space, q), R)
+        assert fro32 <= FP32_REL, f"{space} {q} e={e} fp32: {fro32:.3e}"
+
+
+def test_embedded_geometry_kinds(ctx):
+    """The embedded route on affine and extruded maps (the uniform kernel's metric
+    for each kind, with the per-direction points)."""
+    q = (4, 3, 2)
+    for space in SPACES:
+        assert ctx.aniso_route(space, q) == "embedded", space
+        A = meshgen.affine_parallelepipeds(2, seed=710)
+        o = run(ctx, space, q, A, kind="affine")
+        for e in range(2):
+            fro, mx = rel(elem(o, e, space, q), og.gram(space, q, "affine", A[e]))
+            assert fro <= TOL64 and mx <= TOL64, (space, e)
+        Ex = meshgen.extruded_prisms(2, seed=711)
+        o = run(ctx, space, q, Ex, kind="extruded")
+        T = meshgen.extruded_as_trilinear(Ex)
+        for e in range(2):
+            fro, mx = rel(elem(o, e, space, q), og.gram(space, q, "trilinear", T[e]))
+            assert fro <= TOL64 and mx <= TOL64, (space, e)
+
+
+def test_embedded_chunks(ctx, dpg):
+    """A batch whose order-P scratch exceeds the per-call limit (H(curl) (10, 9, 9):
+    52.7 MB per element, 81 elements per chunk) runs in two chunks; every element
+    against the per-direction kernel, and sampled entries of one element of each
+    chunk against the oracle."""
+    space, q, E = "HCURL", (10, 9, 9), 90
+    assert ctx.aniso_route(space, q) == "embedded"
+    X = meshgen.perturbed_hexes(E, seed=720)
+    g = torch.from_numpy(X).cuda()
+    a = ctx.gram_aniso(space, q, g)
+    b = ctx.gram_aniso(space, q, g, path="general")
+    torch.cuda.synchronize()
+    n = dpg.gram_dim_aniso(space, q)
+    m = n * (n + 1) // 2
+    A, B = a.view(E, m), b.view(E, m)
+    err = ((A - B).abs().amax(dim=1) / B.abs().amax(dim=1)).max().item()
+    say("chunks: max rel diff vs per-direction", err)
+    assert err <= TOL64
+    rng = np.random.default_rng(721)
+    for e in (3, 85):
+        G = og.unpack_upper(A[e].cpu().numpy(), n)
+        I = np.concatenate([np.arange(n), rng.integers(0, n, 2000)])
+        J = np.concatenate([np.arange(n), rng.integers(0, n, 2000)])
+        R = og.gram_entries(space, q, "trilinear", X[e], I, J)
+        assert np.abs(G[I, J] - R).max() / np.abs(G).max() <= TOL64, e
+
+
 @pytest.mark.parametrize("space", SPACES)
 def test_one_rule_for_all_directions(ctx, space):
     """nq > 0: the same nq-point rule in every direction (the shortcut of
@@ -158,13 +233,15 @@ def test_cyclic_relabelling(ctx):
 
 
 def test_bad_element_empty_and_errors(ctx, dpg):
+    """Both routes (embedded by default, per-direction forced) flag and zero a bad element."""
     q = (2, 3, 1)
     X = meshgen.perturbed_hexes(3, seed=660)
     X[1] = X[1][[1, 0, 2, 3, 4, 5, 6, 7]]                  # swap two vertices: det J < 0 somewhere
     st = torch.full((3,), 7, dtype=torch.int32, device="cuda")
-    for space in ("H1", "HDIV"):
-        o = run(ctx, space, q, X, status=st)
-        assert list(st.cpu().numpy()) == [0, dpg.EJACOBIAN, 0]
+    for space, path in (("H1", "auto"), ("HDIV", "auto"), ("H1", "general"), ("HDIV", "general")):
+        st.fill_(7)
+        o = run(ctx, space, q, X, status=st, path=path)
+        assert list(st.cpu().numpy()) == [0, dpg.EJACOBIAN, 0], (space, path)
         m = dpg.gram_dim_aniso(space, q)
         m = m * (m + 1) // 2
         assert np.all(o[m:2 * m] == 0)
@@ -176,6 +253,8 @@ def test_bad_element_empty_and_errors(ctx, dpg):
     for bad in ((0, 1, 1), (1, 11, 1)):
         with pytest.raises(dpg.DpgError):
             ctx.gram_aniso("H1", bad, g)
+        with pytest.raises(dpg.DpgError):
+            ctx.aniso_route("H1", bad)
     with pytest.raises(dpg.DpgError):
         ctx.gram_aniso("H1", q, g, nq=12)
 
