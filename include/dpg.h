@@ -204,11 +204,9 @@ int64_t dpg_noalloc_max_elements(void);
  *     kernels of dpg_gram_integrate's quadrature path; other orders, where order
  *     P = max p_d carries at most about four times the entries needed, the uniform
  *     kernels of order P with each direction on its own rule (zero-weight points
- *     pad it to order P's count) into a scratch buffer, from which the submatrix
- *     is copied out (the 1D bases are hierarchical, Sections 2.4 and 2.8.2).  The
- *     scratch is held by the context (a stream-ordered pool that keeps its memory;
- *     at most 4 GiB per call, batches above run in chunks).  Everything else takes
- *     the per-direction kernel;
+ *     pad it to order P's count), storing only the entries of orders (p1, p2, p3)
+ *     (the 1D bases are hierarchical, Sections 2.4 and 2.8.2; no scratch memory).
+ *     Everything else takes the per-direction kernel;
  *   DPG_PATH_GENERAL: always the per-direction kernel, which contracts the
  *     direction of least order last, in the outermost loop.
  * All routes compute the same sums (rounding aside).  Output, geometry, status,

@@ -104,29 +104,7 @@ int launch_elements(const dpg_ctx* ctx, int space, int p, const dpg_geometry* ge
 dpg_ctx::~dpg_ctx() {
   dpg::destroy_plans(this);
   if (d_tab64) (void)hipFree(d_tab64);
-  if (pool) (void)hipMemPoolDestroy(pool);
 }
-
-namespace dpg {
-
-hipMemPool_t ctx_scratch_pool(const dpg_ctx* ctx) {
-  std::lock_guard<std::mutex> g(ctx->mu);
-  if (!ctx->pool) {
-    hipMemPoolProps props{};
-    props.allocType = hipMemAllocationTypePinned;
-    props.handleTypes = hipMemHandleTypeNone;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = ctx->device;
-    hipMemPool_t pl = nullptr;
-    if (hipMemPoolCreate(&pl, &props) != hipSuccess) return nullptr;
-    uint64_t keep = UINT64_MAX;   // keep the memory between calls
-    (void)hipMemPoolSetAttribute(pl, hipMemPoolAttrReleaseThreshold, &keep);
-    ctx->pool = pl;
-  }
-  return ctx->pool;
-}
-
-}  // namespace dpg
 
 using dpg::fail;
 using dpg::hip_fail;

@@ -62,7 +62,6 @@ struct dpg_ctx {
   mutable std::mutex mu;                                    // guards tune and plans
   mutable std::map<dpg::TuneKey, dpg::TuneVal> tune;
   mutable std::vector<std::shared_ptr<dpg::BatchPlan>> plans;   // most recent last
-  mutable hipMemPool_t pool = nullptr;                      // stream-ordered scratch (created on first use)
   ~dpg_ctx();
 };
 
@@ -92,10 +91,6 @@ int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_g
 bool embed_applies(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts& o);
 int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                           const dpg_opts& o, hipStream_t st);
-
-// The context's scratch pool on its device (memory kept between calls), created on first
-// use; nullptr if the device has none.
-hipMemPool_t ctx_scratch_pool(const dpg_ctx* ctx);
 
 // Load the tuning table shipped with the library (dpg_tables_build).
 int load_default_tune(dpg_ctx* ctx);

@@ -463,9 +463,16 @@ __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real
   }
 }
 
-template <int S, int P, typename Real, int A, int B, bool DIAG>
+// Output numbering of embedded orders (p1, p2, p3) for block (a, b): component a spans
+// R1a x R2a x R3a functions from offset off_a (b likewise); plen packed entries per element.
+struct EmbOut {
+  int R1a, R2a, R3a, R1b, R2b, off_a, off_b;
+  long long plen;
+};
+
+template <int S, int P, typename Real, int A, int B, bool DIAG, bool EMB>
 __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, int t0, int np, int lo,
-                                     bool inl, const Real* sAb, Real* __restrict__ outp) {
+                                     bool inl, const Real* sAb, Real* __restrict__ outp, const EmbOut& eo) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
   using CF = Cfg<S, P, Real>;
@@ -485,7 +492,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
   static_assert(!CF::HD || (A == 0 && B == 0 && BC::NXT == 4 && CF::NB == 1 && NP == 2 && BC::R1b == 8 &&
                             BC::R2b == 8 && BC::NY == 64),
                 "held column heads assume one work item per wave and x-tile over whole j2 rows");
-  const __amdgpu_buffer_rsrc_t rsrc = out_rsrc(outp, packed_len(S, P));
+  // held column heads assume order P's numbering
+  constexpr bool HDE = CF::HD && !EMB;
+  const __amdgpu_buffer_rsrc_t rsrc = out_rsrc(outp, EMB ? eo.plen : packed_len(S, P));
   for (int item = wave; item < CF::NB * XT; item += 4) {
     const int pg = item / XT, xt = item % XT;
     const int npg = imin(NP, np - pg * NP);
@@ -526,23 +535,37 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
       const int s = xt * 16 + lk + 4 * r;
       int i2 = 0, j2 = 0;
       if (s < NXv) decode_x<BC::R2a, DIAG>(sm.xd, s, i2, j2);
-      xa8[r] = s < NXv ? unsigned(BC::R1a * i2 * int(sizeof(Real))) : kDropOff;
-      xb[r] = unsigned(BC::R1b * j2);
+      if constexpr (EMB) {
+        // x outside the embedded orders' (i2, j2) ranges: dropped
+        xa8[r] = s < NXv && i2 < eo.R2a && j2 < eo.R2b ? unsigned(eo.R1a * i2 * int(sizeof(Real))) : kDropOff;
+        xb[r] = unsigned(eo.R1b * j2);
+      } else {
+        xa8[r] = s < NXv ? unsigned(BC::R1a * i2 * int(sizeof(Real))) : kDropOff;
+        xb[r] = unsigned(BC::R1b * j2);
+      }
       xlt[r] = i2 < j2;
     }
     // the pairs' uniform row and column bases
     int Ibp[NP], Jbp[NP];
+    bool rok[NP];   // embedded orders: the pair's i3 is inside component A's range
     bool dgp[NP];   // a diagonal pair in the full x tiling: its lower triangle is dropped
     bool hdw[NP], hdf[NP];   // column heads: held back in LDS / written out after this pair
     static_for<NP>([&](auto PI) {
       constexpr int pi = decltype(PI)::value;
       int i3 = 0, j3 = 0;
       if (pi < npg) pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, inl, i3, j3);
-      Ibp[pi] = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
-      Jbp[pi] = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
+      if constexpr (EMB) {
+        Ibp[pi] = eo.off_a + eo.R1a * eo.R2a * i3;
+        Jbp[pi] = eo.off_b + eo.R1b * eo.R2b * j3;
+        rok[pi] = i3 < eo.R3a;
+      } else {
+        Ibp[pi] = Sh::OFF(A) + BC::R1a * BC::R2a * i3;
+        Jbp[pi] = Sh::OFF(B) + BC::R1b * BC::R2b * j3;
+        rok[pi] = true;
+      }
       dgp[pi] = A == B && !DIAG && i3 == j3;
       hdw[pi] = hdf[pi] = false;
-      if constexpr (CF::HD && !DIAG) {
+      if constexpr (HDE && !DIAG) {
         // slab j3 holds its heads back when its first and its diagonal pair fall in different batches
         const int tb = (j3 * (j3 + 1) - lo * (lo + 1)) / 2;
         const bool held = inl && pi < npg && tb / CF::NBP != (tb + j3) / CF::NBP;
@@ -599,7 +622,9 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
         if constexpr (yt < BC::NYM) {
           const int y = yt * 16 + lr;
           const int i1 = y % BC::R1a, j1 = y / BC::R1a;
-          const unsigned ya8 = y < BC::NY ? unsigned((Ib + i1) * int(sizeof(Real))) : kDropOff;
+          bool yok = y < BC::NY;
+          if constexpr (EMB) yok = yok && i1 < eo.R1a && j1 < eo.R1b && rok[pi];
+          const unsigned ya8 = yok ? unsigned((Ib + i1) * int(sizeof(Real))) : kDropOff;
           const unsigned yb = unsigned(Jb + j1);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -631,7 +656,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // the pair's mask and head holding are wave-uniform: one branch per pair, not per store
     auto st_hd = [&](auto PI, auto YC, auto DG, const Acc (&acc1)[YB]) {
       constexpr int pi = decltype(PI)::value;
-      if constexpr (CF::HD && !DIAG) {
+      if constexpr (HDE && !DIAG) {
         if (hdw[pi])
           st_body(PI, YC, DG, std::true_type{}, acc1);
         else
@@ -655,7 +680,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // (j2 = 2 xt, 2 xt + 1), which the same wave held back at the slab's first pair
     auto flush = [&](auto PI) {
       constexpr int pi = decltype(PI)::value;
-      if constexpr (CF::HD && !DIAG) {
+      if constexpr (HDE && !DIAG) {
         if (hdf[pi]) {
           for (int k = lane; k < 16 * CF::LN; k += 64) {
             const int col = k / CF::LN, row = k % CF::LN;
@@ -705,14 +730,15 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // groups (xor 16, 32) complete the sum, so every lane group holds G[x = xt*16 + arow(lr)][y].
     // Lane group lk then stores the lk-th tail y, with the masks of the MFMA tiles' stores.
     if constexpr (BC::YV) {
-      static_assert(!CF::HD, "held column heads need whole y-tiles");
+      static_assert(!HDE, "held column heads need whole y-tiles");
       const int xs = xt * 16 + M::arow(lr);
       int i2 = 0, j2 = 0;
       if (xs < NXv) decode_x<BC::R2a, DIAG>(sm.xd, xs, i2, j2);
       const int yl = BC::NYM * 16 + lk;
       const int i1 = yl % BC::R1a, j1 = yl / BC::R1a;
-      const int il = i1 + BC::R1a * i2, jl = j1 + BC::R1b * j2;
-      const bool ok = xs < NXv && lk < BC::YTAIL && (!DIAG || i2 < j2 || i1 <= j1);
+      const int il = i1 + (EMB ? eo.R1a : BC::R1a) * i2, jl = j1 + (EMB ? eo.R1b : BC::R1b) * j2;
+      bool ok = xs < NXv && lk < BC::YTAIL && (!DIAG || i2 < j2 || i1 <= j1);
+      if constexpr (EMB) ok = ok && i1 < eo.R1a && j1 < eo.R1b && i2 < eo.R2a && j2 < eo.R2b;
       static_for<NP>([&](auto PI) {
         constexpr int pi = decltype(PI)::value;
         if (pi < npg) {
@@ -737,7 +763,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
           });
           const unsigned J = unsigned(Jbp[pi] + jl);
           const unsigned off = (unsigned(Ibp[pi] + il) + ((__umul24(J, J) + J) >> 1)) * unsigned(sizeof(Real));
-          const bool keep = ok && (!dgp[pi] || il <= jl);
+          const bool keep = ok && rok[pi] && (!dgp[pi] || il <= jl);
           store_out(v, rsrc, int(keep ? off : kDropOff));
         }
       });
@@ -885,6 +911,13 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   };
   Real* sA = static_cast<Real*>(sm.A);
   constexpr int ASTRIDE = CF::NB * CF::AONE;
+  EmbOut eo{};
+  if constexpr (EMB) {
+    eo.R1a = ga.emb_R[A][0]; eo.R2a = ga.emb_R[A][1]; eo.R3a = ga.emb_R[A][2];
+    eo.R1b = ga.emb_R[B][0]; eo.R2b = ga.emb_R[B][1];
+    eo.off_a = ga.emb_off[A]; eo.off_b = ga.emb_off[B];
+    eo.plen = ga.packed_len;
+  }
   if (nbt > 0) {
     bool dg; int t0, np;
     batch(0, dg, t0, np);
@@ -902,8 +935,8 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
         stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA + ((b + 1) & 1) * ASTRIDE);
       }
     }
-    if (dg) work<S, P, Real, A, B, true>(sm, rg, t0, np, j3_lo, inl, cur, outp);
-    else work<S, P, Real, A, B, false>(sm, rg, t0, np, j3_lo, inl, cur, outp);
+    if (dg) work<S, P, Real, A, B, true, EMB>(sm, rg, t0, np, j3_lo, inl, cur, outp, eo);
+    else work<S, P, Real, A, B, false, EMB>(sm, rg, t0, np, j3_lo, inl, cur, outp, eo);
     __syncthreads();
     if constexpr (CF::ABUF == 1) {
       if (b + 1 < nbt) {
@@ -1031,7 +1064,15 @@ __device__ __forceinline__ void general_body(const GeneralArgs& ga) {
         if (!bad) bad = run_block<S, P, Real, 2, 2, EMB>(ga, sm, lo, hi, outp);
       }
     }
-    if (bad) {
+    if (EMB && bad) {
+      // the embedded orders' columns of this group's slabs, component by component
+      for (int b = 0; b < Sh::NC; ++b) {
+        if (!jr(b, lo, hi)) continue;
+        const int64_t w = int64_t(ga.emb_R[b][0]) * ga.emb_R[b][1];
+        const int64_t J0 = ga.emb_off[b] + w * lo, J1 = ga.emb_off[b] + w * hi;
+        for (int64_t i = J0 * (J0 + 1) / 2 + tid; i < J1 * (J1 + 1) / 2; i += NTHREADS) outp[i] = Real(0);
+      }
+    } else if (bad) {
       // element with det J <= 0: its whole output is zero (every slab group does its part)
       auto colstart = [&](int slab) {   // first column J of a slab
         int b = 0, j3 = slab;

@@ -43,13 +43,17 @@ struct GeneralArgs {
                              // triangular x tiling, 1 each closing its slab (full x tiling)
   const int32_t* list;       // listed launch: {item count, first entry in elem_ids} in device
                              // memory (nullptr: n_items and elem_ids as given)
-  // Per-direction rules embedded in the order of the launch (launch_embed_*): direction d
-  // takes the emb_L[d]-point rule (table blocks emb_tab64[d], emb_tabR[d]), and component b
-  // only its column slabs j3 < emb_jmax[b].
+  // Orders (p1, p2, p3) embedded in the order of the launch (launch_embed_*): direction d
+  // takes the emb_L[d]-point rule (table blocks emb_tab64[d], emb_tabR[d]), component b
+  // only its column slabs j3 < emb_jmax[b], and the output is numbered by the embedded
+  // orders: component a spans emb_R[a][d] functions in direction d from emb_off[a]
+  // (packed_len is then that numbering's packed length).
   const double* emb_tab64[3];
   const void* emb_tabR[3];
   int emb_L[3];
   int emb_jmax[3];
+  int emb_R[3][3];
+  int emb_off[4];
 };
 
 // Workgroups of a listed launch (the item count is on the device): enough to fill the
@@ -82,8 +86,8 @@ hipError_t launch_general_list_hcurl(int p, int prec, const GeneralArgs& a, hipS
 hipError_t launch_general_list_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_general_list_l2(int p, int prec, const GeneralArgs& a, hipStream_t s);
 
-// General path with per-direction rules embedded in order p (GeneralArgs::emb_*): the
-// output has order p's numbering.
+// General path with orders embedded in order p (GeneralArgs::emb_*), output in the
+// embedded orders' numbering.
 hipError_t launch_embed_h1(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_embed_hcurl(int p, int prec, const GeneralArgs& a, hipStream_t s);
 hipError_t launch_embed_hdiv(int p, int prec, const GeneralArgs& a, hipStream_t s);

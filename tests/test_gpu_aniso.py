@@ -160,11 +160,10 @@ def test_embedded_geometry_kinds(ctx):
             assert fro <= TOL64 and mx <= TOL64, (space, e)
 
 
-def test_embedded_chunks(ctx, dpg):
-    """A batch whose order-P scratch exceeds the per-call limit (H(curl) (10, 9, 9):
-    52.7 MB per element, 81 elements per chunk) runs in two chunks; every element
-    against the per-direction kernel, and sampled entries of one element of each
-    chunk against the oracle."""
+def test_embedded_high_order_batch(ctx, dpg):
+    """H(curl) (10, 9, 9), 90 elements (several slab groups per element, the largest
+    order of the embedded kernels): every element against the per-direction kernel,
+    and sampled entries of two elements against the oracle."""
     space, q, E = "HCURL", (10, 9, 9), 90
     assert ctx.aniso_route(space, q) == "embedded"
     X = meshgen.perturbed_hexes(E, seed=720)
@@ -176,7 +175,7 @@ def test_embedded_chunks(ctx, dpg):
     m = n * (n + 1) // 2
     A, B = a.view(E, m), b.view(E, m)
     err = ((A - B).abs().amax(dim=1) / B.abs().amax(dim=1)).max().item()
-    say("chunks: max rel diff vs per-direction", err)
+    say("HCURL (10, 9, 9): max rel diff vs per-direction", err)
     assert err <= TOL64
     rng = np.random.default_rng(721)
     for e in (3, 85):
