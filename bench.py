@@ -139,6 +139,8 @@ def main():
                          "(0: skip the serving measurement)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 4 GiB device copy (counter calibration)")
+    ap.add_argument("--aniso-only", action="store_true",
+                    help="run only the non-uniform-order rows (both routes)")
     ap.add_argument("--condense-only", action="store_true",
                     help="run only the condensation measurement (factor and solve of 1024 H1 p=7 Grams)")
     a = ap.parse_args()
@@ -170,6 +172,10 @@ def main():
     ctx = dpg.Context(p_max=11)
     if a.condense_only:
         print(json.dumps({"condense_h1_p7": run_condense(ctx, dpg, stream)}), flush=True)
+        ctx.close()
+        return
+    if a.aniso_only:
+        print(json.dumps({"aniso_orders": run_aniso(ctx, dpg, stream)}), flush=True)
         ctx.close()
         return
     E, space, p = 4096, "H1", 7
@@ -294,6 +300,44 @@ def run_condense(ctx, dpg, stream):
     return row
 
 
+def run_aniso(ctx, dpg, stream):
+    """Non-uniform orders (p1, p2, p3), one rule per coordinate: the route the entry point
+    takes (orders embedded in the uniform kernel of order max p_d) and the per-direction
+    kernel (least order outermost); (7, 7, 7) also through the uniform kernel."""
+    import numpy as np
+    import torch
+    import meshgen
+    ani = []
+    for space, q in (("H1", (7, 6, 5)), ("H1", (7, 7, 7)), ("HCURL", (6, 5, 4)), ("HDIV", (5, 6, 4)),
+                     ("L2", (8, 7, 6))):
+        nd = dpg.gram_dim_aniso(space, q)
+        mm = nd * (nd + 1) // 2
+        n_a = int(min(4096, (2 << 30) // (mm * 8)))
+        Xa = torch.from_numpy(meshgen.perturbed_hexes(n_a, noise=0.15, seed=1712)).cuda()
+        o = torch.empty(n_a * mm, dtype=torch.float64, device="cuda")
+        # nq = the default rule: equal orders stay on the generic kernel (nq = 0 would take the uniform one)
+        nqa = max(q) + 1 if space != "L2" else max(q)
+        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, nq=nqa if len(set(q)) == 1 else 0,
+                                                     stream=stream), 3, 1, stream)
+        kk = float(np.mean(pr))
+        route = ctx.aniso_route(space, q, nq=nqa if len(set(q)) == 1 else 0)
+        row = {"space": space, "p": list(q), "n_elem": n_a, "route": route, "kernel_ms": round(kk, 3),
+               "elements_per_s": round(n_a / (kk * 1e-3), 1),
+               "hbm_gbs": round(mm * 8 * n_a / (kk * 1e-3) / 1e9, 1)}
+        if route == "embedded":
+            w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, path="general", stream=stream),
+                                  3, 1, stream)
+            row["per_direction_ms"] = round(float(np.mean(pr)), 3)
+        if len(set(q)) == 1:
+            w, pr = time_launches(lambda: ctx.gram(space, q[0], Xa, out=o, stream=stream), 3, 1, stream)
+            row["uniform_kernel_ms"] = round(float(np.mean(pr)), 3)
+        ani.append(row)
+        log(f"[bench] extra aniso {row}")
+        del o, Xa
+        torch.cuda.empty_cache()
+    return ani
+
+
 def run_extra(ctx, dpg, stream, E, X, out64):
     """FP32 on the benchmark workload; affine and extruded reduced vs general;
     an uneven-order batch.  Small repeat counts; every rate is elements/s."""
@@ -353,38 +397,7 @@ def run_extra(ctx, dpg, stream, E, X, out64):
                                  "hbm_frac": round(moved / (kk * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     log(f"[bench] extra replicate {res['replicate_h1_p7_x3']}")
     del src, dst
-    # non-uniform orders (p1, p2, p3), one rule per coordinate: the route the entry point takes
-    # (orders embedded in the uniform kernel of order max p_d) and the per-direction kernel
-    # (least order outermost); (7, 7, 7) also through the uniform kernel for comparison
-    ani = []
-    for space, q in (("H1", (7, 6, 5)), ("H1", (7, 7, 7)), ("HCURL", (6, 5, 4)), ("HDIV", (5, 6, 4)),
-                     ("L2", (8, 7, 6))):
-        nd = dpg.gram_dim_aniso(space, q)
-        mm = nd * (nd + 1) // 2
-        n_a = int(min(4096, (2 << 30) // (mm * 8)))
-        Xa = torch.from_numpy(meshgen.perturbed_hexes(n_a, noise=0.15, seed=1712)).cuda()
-        o = torch.empty(n_a * mm, dtype=torch.float64, device="cuda")
-        # nq = the default rule: equal orders stay on the generic kernel (nq = 0 would take the uniform one)
-        nqa = max(q) + 1 if space != "L2" else max(q)
-        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, nq=nqa if len(set(q)) == 1 else 0,
-                                                     stream=stream), 3, 1, stream)
-        kk = float(np.mean(pr))
-        route = ctx.aniso_route(space, q, nq=nqa if len(set(q)) == 1 else 0)
-        row = {"space": space, "p": list(q), "n_elem": n_a, "route": route, "kernel_ms": round(kk, 3),
-               "elements_per_s": round(n_a / (kk * 1e-3), 1),
-               "hbm_gbs": round(mm * 8 * n_a / (kk * 1e-3) / 1e9, 1)}
-        if route == "embedded":
-            w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, path="general", stream=stream),
-                                  3, 1, stream)
-            row["per_direction_ms"] = round(float(np.mean(pr)), 3)
-        if len(set(q)) == 1:
-            w, pr = time_launches(lambda: ctx.gram(space, q[0], Xa, out=o, stream=stream), 3, 1, stream)
-            row["uniform_kernel_ms"] = round(float(np.mean(pr)), 3)
-        ani.append(row)
-        log(f"[bench] extra aniso {row}")
-        del o, Xa
-        torch.cuda.empty_cache()
-    res["aniso_orders"] = ani
+    res["aniso_orders"] = run_aniso(ctx, dpg, stream)
 
     res["condense_h1_p7"] = run_condense(ctx, dpg, stream)
     # adjoint graph coupling block (one constant matrix per order)
