@@ -343,6 +343,9 @@ def test_chunked_request_all_or_none():
         s.submit_chunked("H1", 3, geom(5), dp=1, max_chunk_bytes=per // 2)
     assert e.value.code == dpg.EINVAL
     busy = [s.submit("H1", 3, geom(10), dp=1) for _ in range(3)]   # the head runs, two wait
+    t0 = time.time()
+    while s.stats()["admitted"] < 1 and time.time() - t0 < 10:  # the scheduler thread admits the head
+        time.sleep(0.001)
     with pytest.raises(dpg.DpgError) as e:                       # 4 chunks, 3 free queue entries at most
         s.submit_chunked("H1", 3, geom(40), dp=1)
     assert e.value.code == dpg.EAGAIN
