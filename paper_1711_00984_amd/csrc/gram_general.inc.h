@@ -311,12 +311,12 @@ __device__ __forceinline__ void store_out(float v, __amdgpu_buffer_rsrc_t r, int
 // (j3, j3) of a diagonal block.  A batch is a run [t0, t0 + np) of one list.
 // ---------------------------------------------------------------------------
 template <int S, int P, int A, int B>
-__device__ __forceinline__ void pair_of(bool diag, int t, int lo, bool inl, int& i3, int& j3) {
-  using BC = Blk<S, P, A, B>;
+// r3a: the i3 range of a block a < b (R3(A), or the embedded orders' range)
+__device__ __forceinline__ void pair_of(bool diag, int t, int lo, bool inl, int& i3, int& j3, int r3a) {
   if (diag) { i3 = lo + t; j3 = lo + t; return; }
   if constexpr (A != B) {
-    j3 = lo + t / BC::R3a;
-    i3 = t % BC::R3a;
+    j3 = lo + t / r3a;
+    i3 = t % r3a;
   } else if (inl) {
     // i3 = 0 .. j3 inclusive: the diagonal pair closes its slab
     int j = lo;
@@ -411,7 +411,7 @@ template <int S, int P, typename Real, int A, int B> struct Regs {
 // stage 3: A[pg][(q, m)][row(pi, l)] = sum_n c(l, m, n) T_i3(n) T_j3(n) for the batch's pairs
 template <int S, int P, typename Real, int A, int B>
 __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real, A, B>& rg, bool diag, int t0,
-                                       int np, int lo, bool inl, Real* sAb) {
+                                       int np, int lo, bool inl, Real* sAb, int r3a) {
   using Sh = Shape<S, P>;
   using BC = Blk<S, P, A, B>;
   using CF = Cfg<S, P, Real>;
@@ -428,7 +428,7 @@ __device__ __forceinline__ void stage3(const SmemPtrs& sm, const Regs<S, P, Real
     const int l = idx % L, m = (idx / L) % L, k = idx / L2;
     if (k >= np) continue;
     int i3, j3;
-    pair_of<S, P, A, B>(diag, t0 + k, lo, inl, i3, j3);
+    pair_of<S, P, A, B>(diag, t0 + k, lo, inl, i3, j3, r3a);
     const int pg = k / BC::NP, pi = k % BC::NP;
     const int ka = i3 + Sh::SH(A, 2), kb = j3 + Sh::SH(B, 2);
     Real* dst = sAb + pg * CF::AONE + m * 16 + M::crow(l & 3, pi * BC::RPP + (l >> 2));
@@ -553,7 +553,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     static_for<NP>([&](auto PI) {
       constexpr int pi = decltype(PI)::value;
       int i3 = 0, j3 = 0;
-      if (pi < npg) pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, inl, i3, j3);
+      if (pi < npg) pair_of<S, P, A, B>(DIAG, t0 + pg * NP + pi, lo, inl, i3, j3, EMB ? eo.R3a : BC::R3a);
       if constexpr (EMB) {
         Ibp[pi] = eo.off_a + eo.R1a * eo.R2a * i3;
         Jbp[pi] = eo.off_b + eo.R1b * eo.R2b * j3;
@@ -899,7 +899,9 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   // diagonal pairs either close their slab in the full x tiling (inl) or come last, in
   // batches of their own with the triangular x tiling
   const bool inl = diag_inline_ok(S, P) && ga.diag_inline != 0;
-  const int n_nd = A != B ? BC::R3a * (j3_hi - j3_lo)
+  // blocks a < b of embedded orders only run the rows i3 of those orders
+  const int r3a = EMB ? ga.emb_R[A][2] : BC::R3a;
+  const int n_nd = A != B ? r3a * (j3_hi - j3_lo)
                  : inl ? (j3_hi * (j3_hi + 1) - j3_lo * (j3_lo + 1)) / 2
                        : (j3_hi * (j3_hi - 1) - j3_lo * (j3_lo - 1)) / 2;
   const int n_d = A == B && !inl ? j3_hi - j3_lo : 0;
@@ -921,7 +923,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
   if (nbt > 0) {
     bool dg; int t0, np;
     batch(0, dg, t0, np);
-    stage3<S, P, Real, A, B>(sm, rg, dg, t0, np, j3_lo, inl, sA);
+    stage3<S, P, Real, A, B>(sm, rg, dg, t0, np, j3_lo, inl, sA, r3a);
   }
   __syncthreads();
   for (int b = 0; b < nbt; ++b) {
@@ -932,7 +934,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       if (b + 1 < nbt) {
         bool dn; int tn, nn;
         batch(b + 1, dn, tn, nn);
-        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA + ((b + 1) & 1) * ASTRIDE);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA + ((b + 1) & 1) * ASTRIDE, r3a);
       }
     }
     if (dg) work<S, P, Real, A, B, true, EMB>(sm, rg, t0, np, j3_lo, inl, cur, outp, eo);
@@ -942,7 +944,7 @@ __device__ __forceinline__ bool run_block(const GeneralArgs& ga, const SmemPtrs 
       if (b + 1 < nbt) {
         bool dn; int tn, nn;
         batch(b + 1, dn, tn, nn);
-        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA);
+        stage3<S, P, Real, A, B>(sm, rg, dn, tn, nn, j3_lo, inl, sA, r3a);
         __syncthreads();
       }
     }
