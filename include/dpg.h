@@ -361,11 +361,17 @@ typedef struct {
   int32_t geom_on_host;    /* 1: geom.data is host memory, 0: device memory        */
   dpg_geometry geom;       /* copied at submit; the caller may reuse it at once    */
   double w0, w1;           /* weights of the value / derivative parts              */
+  int32_t pdir[3];         /* non-uniform trial orders per direction (all > 0; the
+                              Gram orders pdir[d] + dp, each <= 10 and <= ctx p_max;
+                              p is then ignored) as dpg_gram_integrate_aniso with the
+                              default rule; all zero: the uniform order p            */
+  int32_t reserved;        /* 0 */
 } dpg_request;
 
 typedef struct {
   int32_t status;          /* DPG_OK, or the error that failed the request          */
-  int32_t space, p, prec;  /* p = Gram order                                        */
+  int32_t space, p, prec;  /* p = Gram order (the largest per-direction one for
+                              non-uniform orders; packed_len gives the size)       */
   int64_t n_elem;
   int64_t packed_len;      /* entries per element                                   */
   void* out;               /* device, n_elem * packed_len entries (NULL: stub)      */

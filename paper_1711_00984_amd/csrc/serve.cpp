@@ -116,8 +116,18 @@ class HipExecutor final : public Executor {
                          hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return hip_fail(e, "geometry upload");
     }
-    int rc;
-    if (l.work.size() == 1) {
+    int rc = DPG_OK;
+    if (w0.q[0] > 0) {
+      // non-uniform orders: one call per request (its slots and output range are contiguous),
+      // through the entry point's route for the orders
+      for (const Work& w : l.work) {
+        if (w.slot0 + w.n > slots_ || w.out_off % es) return fail(DPG_EINVAL, "request outside the arenas");
+        dpg_geometry g{w.kind, 0, w.n, geo + w.slot0 * gs};
+        o.status = status_ + w.slot0;
+        rc = dpg_gram_integrate_aniso(ctx_, w.space, w.q, &g, out_ + w.out_off, &o, st);
+        if (rc != DPG_OK) break;
+      }
+    } else if (l.work.size() == 1) {
       // one request: its slots and its output range are contiguous
       if (w0.slot0 + w0.n > slots_ || w0.out_off % es) return fail(DPG_EINVAL, "request outside the arenas");
       dpg_geometry g{w0.kind, 0, w0.n, geo + w0.slot0 * gs};

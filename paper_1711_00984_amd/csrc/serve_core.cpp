@@ -58,7 +58,7 @@ int elem_bytes(int prec) { return prec == DPG_FP32 ? 4 : 8; }
 
 bool same_key(const Work& a, const Work& b) {
   return a.space == b.space && a.p == b.p && a.prec == b.prec && a.path == b.path && a.kind == b.kind &&
-         a.w0 == b.w0 && a.w1 == b.w1;
+         a.w0 == b.w0 && a.w1 == b.w1 && a.q[0] == b.q[0] && a.q[1] == b.q[1] && a.q[2] == b.q[2];
 }
 
 // nearest-rank percentile of an unsorted sample (copied)
@@ -102,8 +102,20 @@ double Server::now() const {
 
 int Server::prepare(const dpg_request& rq, Req& r, double t_submit) {
   if (rq.space < DPG_H1 || rq.space > DPG_L2) return fail(DPG_EINVAL, "unknown space %d", rq.space);
-  if (rq.p < 1 || rq.dp < 0 || rq.p + rq.dp > p_max_)
+  const bool aniso = rq.pdir[0] != 0 || rq.pdir[1] != 0 || rq.pdir[2] != 0;
+  int32_t q[3] = {0, 0, 0};
+  if (aniso) {
+    // non-uniform orders: the per-direction Gram orders, each within the kernels' range
+    const int qmax = p_max_ < 10 ? p_max_ : 10;
+    for (int d = 0; d < 3; ++d) {
+      q[d] = rq.pdir[d] + rq.dp;
+      if (rq.pdir[d] < 1 || rq.dp < 0 || q[d] > qmax)
+        return fail(DPG_EINVAL, "pdir[%d]=%d dp=%d: Gram order outside [1, %d]", d, rq.pdir[d], rq.dp, qmax);
+    }
+    if (rq.path == DPG_PATH_REDUCED) return fail(DPG_EINVAL, "non-uniform orders use the quadrature path only");
+  } else if (rq.p < 1 || rq.dp < 0 || rq.p + rq.dp > p_max_) {
     return fail(DPG_EINVAL, "p=%d dp=%d: Gram order outside [1, %d]", rq.p, rq.dp, p_max_);
+  }
   if (rq.prec != DPG_FP64 && rq.prec != DPG_FP32) return fail(DPG_EINVAL, "unknown precision %d", rq.prec);
   if (rq.path < DPG_PATH_AUTO || rq.path > DPG_PATH_REDUCED) return fail(DPG_EINVAL, "unknown path %d", rq.path);
   if (rq.geom.kind != DPG_GEOM_TRILINEAR && rq.geom.kind != DPG_GEOM_AFFINE && rq.geom.kind != DPG_GEOM_EXTRUDED)
@@ -112,17 +124,25 @@ int Server::prepare(const dpg_request& rq, Req& r, double t_submit) {
     return fail(DPG_EINVAL, "the reduced path needs affine or extruded geometry");
   if (rq.geom.n_elem < 1 || !rq.geom.data) return fail(DPG_EINVAL, "empty request or NULL geometry");
   if (!std::isfinite(rq.w0) || !std::isfinite(rq.w1)) return fail(DPG_EINVAL, "weights must be finite");
-  const int pr = rq.p + rq.dp;
+  const int pr = aniso ? (q[0] > q[1] ? (q[0] > q[2] ? q[0] : q[2]) : (q[1] > q[2] ? q[1] : q[2])) : rq.p + rq.dp;
   r = Req{};
   r.w.space = rq.space;
   r.w.p = pr;
+  for (int d = 0; d < 3; ++d) r.w.q[d] = q[d];
   r.w.prec = rq.prec;
   r.w.path = rq.path;
   r.w.kind = rq.geom.kind;
   r.w.w0 = rq.w0;
   r.w.w1 = rq.w1;
   r.w.n = rq.geom.n_elem;
-  r.w.packed_len = packed_len(rq.space, pr);
+  if (aniso) {
+    int64_t nd = 0;   // component a spans range1d(space, q_d, a, d) functions in direction d
+    for (int a = 0; a < ncomp(rq.space); ++a)
+      nd += int64_t(range1d(rq.space, q[0], a, 0)) * range1d(rq.space, q[1], a, 1) * range1d(rq.space, q[2], a, 2);
+    r.w.packed_len = nd * (nd + 1) / 2;
+  } else {
+    r.w.packed_len = packed_len(rq.space, pr);
+  }
   r.t_submit = t_submit;
   const double bytes = double(r.w.n) * double(r.w.packed_len) * elem_bytes(rq.prec);
   if (bytes > double(out_alloc_.capacity()))

@@ -54,6 +54,7 @@ class RangeAlloc {
 struct Work {
   uint64_t ticket = 0;
   int space = 0, p = 0, prec = 0, path = 0, kind = 0;
+  int q[3] = {0, 0, 0};    // non-uniform Gram orders per direction (zeros: the uniform order p)
   double w0 = 1, w1 = 1;
   int64_t n = 0;           // elements
   int64_t slot0 = 0;       // first element slot (geometry, status)

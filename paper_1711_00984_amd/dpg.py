@@ -55,7 +55,8 @@ class ServeCfg(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("space", _i32), ("p", _i32), ("dp", _i32), ("prec", _i32), ("path", _i32),
-                ("geom_on_host", _i32), ("geom", Geometry), ("w0", _d), ("w1", _d)]
+                ("geom_on_host", _i32), ("geom", Geometry), ("w0", _d), ("w1", _d),
+                ("pdir", _i32 * 3), ("reserved", _i32)]
 
 
 class Result(ctypes.Structure):
@@ -512,7 +513,8 @@ class Server:
             pass
 
     def submit(self, space, p, geom, dp=0, kind="trilinear", prec="fp64", path="auto", w0=1.0, w1=1.0):
-        """Queue one request; returns its ticket.  geom: float64 numpy array or
+        """Queue one request; returns its ticket.  p: the trial order, or a triple
+        (p1, p2, p3) of non-uniform trial orders.  geom: float64 numpy array or
         tensor (host or device) of n_elem * 24 (trilinear), * 12 (affine) or
         * 10 (extruded) values, copied before this returns.  Raises DpgError (code EAGAIN when
         the queue or the element slots are full)."""
@@ -546,8 +548,14 @@ class Server:
             ptr, numel, on_host = geom.ctypes.data, geom.size, 1
         if numel % per:
             raise ValueError(f"geometry size {numel} is not a multiple of {per}")
+        pdir = (0, 0, 0)
+        if hasattr(p, "__len__"):
+            pdir, p = tuple(int(x) for x in p), 0
+            if len(pdir) != 3:
+                raise ValueError("non-uniform orders need three values")
         return Request(space_id(space), int(p), int(dp), {"fp64": FP64, "fp32": FP32}.get(prec, prec),
-                       PATHS.get(path, path), on_host, Geometry(kind, 0, numel // per, ptr), float(w0), float(w1))
+                       PATHS.get(path, path), on_host, Geometry(kind, 0, numel // per, ptr), float(w0), float(w1),
+                       (_i32 * 3)(*pdir), 0)
 
     def poll(self, ticket):
         """None while pending; else a dict with status, space, p (Gram order), prec,

@@ -243,3 +243,30 @@ def test_short_poisson_trace(ctx, dpg):
     assert st["completed"] == len(trace) and st["failed"] == 0 and st["lat_p99"] >= st["lat_p50"] > 0
     assert checked == len(keep) and st["admitted_bytes"] == 0
     srv.close()
+
+
+def test_non_uniform_orders_served(ctx, dpg):
+    """Requests of non-uniform orders: each served result equals
+    dpg_gram_integrate_aniso on the same geometry (bitwise: same kernels), the
+    same-order requests in one launch, and one element against the oracle."""
+    say("non-uniform orders")
+    srv = dpg.Server(ctx, mem_budget_bytes=1 << 30, n_streams=2)
+    cases = [("HDIV", (3, 2, 1), 1, 40), ("HDIV", (3, 2, 1), 1, 25), ("H1", (6, 5, 4), 0, 64), ("L2", (3, 4, 2), 1, 9),
+             ("HCURL", (1, 1, 6), 0, 7)]                          # the last one takes the per-direction kernel
+    assert ctx.aniso_route("HCURL", (1, 1, 6)) == "per-direction"
+    geos = [meshgen.perturbed_hexes(n, seed=40 + k) for k, (_, _, _, n) in enumerate(cases)]
+    ts = [srv.submit(sp, q, X.reshape(-1), dp=dp) for (sp, q, dp, _), X in zip(cases, geos)]
+    res = drain(srv, ts)
+    for t, (sp, q, dp, n), X in zip(ts, cases, geos):
+        qq = tuple(x + dp for x in q)
+        assert res[t]["status"] == dpg.OK and res[t]["p"] == max(qq)
+        served = srv.read(t)
+        a = ctx.gram_aniso(sp, qq, torch.from_numpy(X).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(served, a), (sp, q)
+    sp, q, dp, _ = cases[2]
+    nd = shapes.dimension(sp, q)
+    G = og.unpack_upper(srv.read(ts[2]).cpu().numpy()[3 * nd * (nd + 1) // 2:4 * nd * (nd + 1) // 2], nd)
+    R = og.gram(sp, q, "trilinear", geos[2][3])
+    assert np.abs(G - R).max() / np.abs(R).max() <= TOL64
+    srv.close()

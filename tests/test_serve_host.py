@@ -355,3 +355,28 @@ def test_chunked_request_all_or_none():
     assert k == 4
     drain(s, list(range(first, first + k)))
     s.close()
+
+
+def test_non_uniform_orders():
+    """Requests of non-uniform orders (p1, p2, p3): sized by the per-direction Gram
+    orders, merged only with requests of the same orders, validated like the
+    entry point (orders in [1, 10], no reduced path)."""
+    s = dpg.Server(None, test_executor=True, test_launch_s=0.002)
+    t = s.submit("HCURL", (3, 2, 1), geom(20), dp=1)                # Gram orders (4, 3, 2)
+    r = drain(s, [t], release=False)[t]
+    nd = dpg.gram_dim_aniso("HCURL", (4, 3, 2))
+    assert r["status"] == dpg.OK and r["p"] == 4 and r["n_elem"] == 20 and r["packed_len"] == nd * (nd + 1) // 2
+    s.release(t)
+    s.reset_stats()
+    # same orders merge; different orders, or the uniform order, do not
+    ts = [s.submit("H1", (5, 4, 3), geom(10)) for _ in range(3)] + [s.submit("H1", (5, 4, 2), geom(10)),
+                                                                      s.submit("H1", 5, geom(10))]
+    drain(s, ts)
+    assert 3 <= s.stats()["launches"] <= 5
+    for bad in ((0, 2, 3), (1, 2, -1), (10, 2, 2)):
+        with pytest.raises(dpg.DpgError) as e:                      # dp = 1: Gram order 11 > 10
+            s.submit("H1", bad, geom(4), dp=1)
+        assert e.value.code == dpg.EINVAL
+    with pytest.raises(dpg.DpgError):
+        s.submit("H1", (2, 3, 4), geom(4, "affine"), kind="affine", path="reduced")
+    s.close()
