@@ -302,8 +302,8 @@ def run_condense(ctx, dpg, stream):
 
 def run_aniso(ctx, dpg, stream):
     """Non-uniform orders (p1, p2, p3), one rule per coordinate: the route the entry point
-    takes (orders embedded in the uniform kernel of order max p_d) and the per-direction
-    kernel (least order outermost); (7, 7, 7) also through the uniform kernel."""
+    takes (orders embedded in the uniform kernel of order max p_d; equal orders the uniform
+    kernel itself) and the per-direction kernel (least order outermost)."""
     import numpy as np
     import torch
     import meshgen
@@ -315,22 +315,15 @@ def run_aniso(ctx, dpg, stream):
         n_a = int(min(4096, (2 << 30) // (mm * 8)))
         Xa = torch.from_numpy(meshgen.perturbed_hexes(n_a, noise=0.15, seed=1712)).cuda()
         o = torch.empty(n_a * mm, dtype=torch.float64, device="cuda")
-        # nq = the default rule: equal orders stay on the generic kernel (nq = 0 would take the uniform one)
-        nqa = max(q) + 1 if space != "L2" else max(q)
-        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, nq=nqa if len(set(q)) == 1 else 0,
-                                                     stream=stream), 3, 1, stream)
+        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, stream=stream), 3, 1, stream)
         kk = float(np.mean(pr))
-        route = ctx.aniso_route(space, q, nq=nqa if len(set(q)) == 1 else 0)
+        route = ctx.aniso_route(space, q)
         row = {"space": space, "p": list(q), "n_elem": n_a, "route": route, "kernel_ms": round(kk, 3),
                "elements_per_s": round(n_a / (kk * 1e-3), 1),
                "hbm_gbs": round(mm * 8 * n_a / (kk * 1e-3) / 1e9, 1)}
-        if route == "embedded":
-            w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, path="general", stream=stream),
-                                  3, 1, stream)
-            row["per_direction_ms"] = round(float(np.mean(pr)), 3)
-        if len(set(q)) == 1:
-            w, pr = time_launches(lambda: ctx.gram(space, q[0], Xa, out=o, stream=stream), 3, 1, stream)
-            row["uniform_kernel_ms"] = round(float(np.mean(pr)), 3)
+        w, pr = time_launches(lambda: ctx.gram_aniso(space, q, Xa, out=o, path="general", stream=stream),
+                              3, 1, stream)
+        row["per_direction_ms"] = round(float(np.mean(pr)), 3)
         ani.append(row)
         log(f"[bench] extra aniso {row}")
         del o, Xa

@@ -105,7 +105,7 @@ typedef struct {
  * (xi2, xi3) for extruded maps (Algorithm 11).  nq: Gauss-Legendre points
  * per direction of the quadrature path, 0 = default (p+1; p for L2, exact
  * for degree 2 nq - 1 on (0,1), text after (2.22)).  dpg_gram_integrate runs
- * a rule other than the default on the generic kernel of
+ * a rule other than the default through the AUTO routes of
  * dpg_gram_integrate_aniso at orders (p, p, p) (nq in [1, 11], p <= 10; AUTO
  * then takes the quadrature path for every geometry kind, REDUCED is
  * rejected: it integrates exactly).  The batched call takes the default only.
@@ -201,12 +201,13 @@ int64_t dpg_noalloc_max_elements(void);
  * coordinate takes its own Gauss rule (p_d + 1 points, p_d for L2), or opts->nq
  * points in every direction when nq > 0 (at most 11).  Kernels, by opts->path:
  *   DPG_PATH_AUTO: with the default rule (nq = 0), equal orders take the uniform
- *     kernels of dpg_gram_integrate's quadrature path; other orders, where order
- *     P = max p_d carries at most about four times the entries needed, the uniform
- *     kernels of order P with each direction on its own rule (zero-weight points
- *     pad it to order P's count), storing only the entries of orders (p1, p2, p3)
- *     (the 1D bases are hierarchical, Sections 2.4 and 2.8.2; no scratch memory).
- *     Everything else takes the per-direction kernel;
+ *     kernels of dpg_gram_integrate's quadrature path.  Other orders and explicit
+ *     rules, where order P = max p_d (raised, for nq > 0, to the order whose default
+ *     rule has nq points; P <= 10) carries at most about four times the entries
+ *     needed, take the uniform kernels of order P with each direction on its own
+ *     rule (zero-weight points pad it to order P's count), storing only the entries
+ *     of orders (p1, p2, p3) (the 1D bases are hierarchical, Sections 2.4 and
+ *     2.8.2; no scratch memory).  Everything else takes the per-direction kernel;
  *   DPG_PATH_GENERAL: always the per-direction kernel, which contracts the
  *     direction of least order last, in the outermost loop.
  * All routes compute the same sums (rounding aside).  Output, geometry, status,

@@ -7,7 +7,8 @@
 // direction d on its p_d rule, padded to order P's point count with zero-weight
 // points, only over the column slabs j3 < R3(p3) the submatrix needs, and stores the
 // submatrix's entries straight into the packed numbering of (p1, p2, p3) (the others
-// are dropped at the store).
+// are dropped at the store).  An explicit rule of nq points in every direction embeds
+// the same way, in an order whose default rule has at least nq points.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -20,16 +21,18 @@ namespace dpg {
 
 namespace {
 
-int emb_order(const int32_t* p) {
+// The order of the launch: the largest p_d, raised so that its default rule has at
+// least the nq points of an explicit rule.
+int emb_order(int space, const int32_t* p, int nq) {
   int P = p[0];
   for (int d = 1; d < 3; ++d) P = p[d] > P ? p[d] : P;
-  return P;
+  const int Pq = space == SP_L2 ? nq : nq - 1;
+  return Pq > P ? Pq : P;
 }
 
 // Unknowns the order-P launch carries: the columns of the slabs j3 < R3(p3) of each
 // component.
-int64_t emb_columns(int space, const int32_t* p) {
-  const int P = emb_order(p);
+int64_t emb_columns(int space, const int32_t* p, int P) {
   int64_t n = 0;
   for (int b = 0; b < ncomp(space); ++b)
     n += int64_t(range1d(space, P, b, 0)) * range1d(space, P, b, 1) * range1d(space, p[2], b, 2);
@@ -39,21 +42,21 @@ int64_t emb_columns(int space, const int32_t* p) {
 }  // namespace
 
 bool embed_applies(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts& o) {
-  if (o.nq != 0 || o.path != DPG_PATH_AUTO) return false;
-  const int P = emb_order(p);
+  if (o.nq < 0 || o.path != DPG_PATH_AUTO) return false;
+  const int P = emb_order(space, p, o.nq);
   if (P > 10 || P > ctx->p_max) return false;
   int64_t na = 0;
   for (int a = 0; a < ncomp(space); ++a)
     na += int64_t(range1d(space, p[0], a, 0)) * range1d(space, p[1], a, 1) * range1d(space, p[2], a, 2);
   // the order-P launch computes about (columns / unknowns)^2 times the entries needed;
   // the uniform kernels run the same sums 5-8x faster than the per-direction kernel
-  const double r = double(emb_columns(space, p)) / double(na);
+  const double r = double(emb_columns(space, p, P)) / double(na);
   return r * r <= 4.0;
 }
 
 int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
                           const dpg_opts& o, hipStream_t st) {
-  const int P = emb_order(p);
+  const int P = emb_order(space, p, o.nq);
   const int nc = ncomp(space);
   GeneralArgs a{};
   a.geom = geom->data;
@@ -68,7 +71,7 @@ int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const
   a.tabR = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + table_offset(L))
                               : static_cast<const void*>(ctx->d_tab64 + table_offset(L));
   for (int d = 0; d < 3; ++d) {
-    const int Ld = npoints(space, p[d]);
+    const int Ld = o.nq > 0 ? o.nq : npoints(space, p[d]);
     a.emb_L[d] = Ld;
     a.emb_tab64[d] = ctx->d_tab64 + table_offset(Ld);
     a.emb_tabR[d] = o.prec == DPG_FP32 ? static_cast<const void*>(ctx->d_tab32 + table_offset(Ld))

@@ -228,9 +228,10 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
   if (!dpg::valid_space(space)) return fail(DPG_EINVAL, "unknown space %d", space);
   if (p < 1 || p > ctx->p_max) return fail(DPG_EINVAL, "p=%d outside [1, %d]", p, ctx->p_max);
   if (o.nq != 0 && o.nq != dpg::npoints(space, p)) {
-    // A rule other than the default: the quadrature path with nq points per direction.  The
-    // uniform kernels are built for the default rule only, so the generic kernel of
-    // non-uniform orders integrates it, at orders (p, p, p).
+    // A rule other than the default: the quadrature path with nq points per direction, at
+    // orders (p, p, p) through the routes of non-uniform orders (the uniform kernel of an
+    // order whose rule has at least nq points, padded with zero-weight points, or the
+    // per-direction kernel).
     if (o.path == DPG_PATH_REDUCED)
       return fail(DPG_EINVAL, "nq=%d: the reduced path integrates exactly and takes no rule", o.nq);
     if (o.nq < 1 || o.nq > dpg::ANISO_LMAX)
@@ -240,6 +241,10 @@ int dpg_gram_integrate(const dpg_ctx* ctx, int space, int p, const dpg_geometry*
                   dpg::ANISO_PMAX);
     if (geom->n_elem == 0) return DPG_OK;
     const int32_t q[3] = {p, p, p};
+    dpg_opts a = o;
+    a.path = DPG_PATH_AUTO;   // GENERAL here names the quadrature path, not the per-direction kernel
+    if (dpg::embed_applies(ctx, space, q, a))
+      return dpg::integrate_aniso_embed(ctx, space, q, geom, out, a, static_cast<hipStream_t>(stream));
     return dpg::integrate_aniso(ctx, space, q, geom, out, o, static_cast<hipStream_t>(stream));
   }
   if (geom->n_elem == 0) return DPG_OK;

@@ -98,18 +98,45 @@ def test_aniso_high_orders(ctx, space, q):
 @pytest.mark.parametrize("space", SPACES)
 @pytest.mark.parametrize("p", [2, 5])
 def test_uniform_orders_match_the_uniform_kernels(ctx, space, p):
-    """Equal orders: the generic kernel (forced by an explicit nq equal to the
-    default rule) against the uniform kernels, which the entry point itself takes
-    for nq = 0 (bit for bit the uniform call)."""
+    """Equal orders: the per-direction kernel (path GENERAL) and the embedded route
+    (an explicit nq equal to the default rule) against the uniform kernels, which the
+    entry point itself takes for nq = 0 (bit for bit the uniform call)."""
     X = meshgen.perturbed_hexes(4, seed=620 + p)
     L = p if space == "L2" else p + 1
-    a = run(ctx, space, (p, p, p), X, nq=L)
+    assert ctx.aniso_route(space, (p, p, p)) == "uniform"
+    assert ctx.aniso_route(space, (p, p, p), nq=L) == "embedded"
+    a = run(ctx, space, (p, p, p), X, nq=L, path="general")
+    b = run(ctx, space, (p, p, p), X, nq=L)
     d = run(ctx, space, (p, p, p), X)
     u = ctx.gram(space, p, torch.from_numpy(X).cuda(), path="general").cpu().numpy()
     assert np.array_equal(d, u)
     for e in range(4):
-        fro, mx = rel(elem(a, e, space, (p,) * 3), elem(u, e, space, (p,) * 3))
-        assert fro <= TOL64 and mx <= TOL64, f"{space} p={p} e={e}"
+        for o in (a, b):
+            fro, mx = rel(elem(o, e, space, (p,) * 3), elem(u, e, space, (p,) * 3))
+            assert fro <= TOL64 and mx <= TOL64, f"{space} p={p} e={e}"
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("q,nq", [((4, 4, 3), 5), ((3, 3, 3), 2), ((5, 5, 5), 8)])
+def test_explicit_rule_routes(ctx, dpg, space, q, nq):
+    """An explicit rule of nq points in every direction: embedded in the uniform
+    kernel of an order whose default rule has at least nq points (padded with
+    zero-weight points) where that carries at most about four times the entries,
+    else the per-direction kernel; both against the oracle with the same rule, and
+    dpg_gram_integrate with nq at equal orders against the aniso call."""
+    want = "per-direction" if (space, q, nq) == ("L2", (5, 5, 5), 8) else "embedded"
+    assert ctx.aniso_route(space, q, nq=nq) == want
+    X = meshgen.perturbed_hexes(2, seed=680 + nq)
+    o = run(ctx, space, q, X, nq=nq)
+    g = run(ctx, space, q, X, nq=nq, path="general")
+    for e in range(2):
+        R = og.gram(space, q, "trilinear", X[e], L=nq)
+        for out in (o, g):
+            fro, mx = rel(elem(out, e, space, q), R)
+            assert fro <= TOL64 and mx <= TOL64, f"{space} {q} nq={nq} e={e}: {fro:.3e} {mx:.3e}"
+    if len(set(q)) == 1:
+        u = ctx.gram(space, q[0], torch.from_numpy(X).cuda(), nq=nq, path="general").cpu().numpy()
+        assert np.array_equal(u, o)
 
 
 EMBEDDED = [("H1", (7, 6, 5)), ("H1", (3, 1, 2)), ("H1", (10, 9, 8)), ("HCURL", (6, 5, 4)), ("HCURL", (2, 3, 1)),
@@ -119,12 +146,11 @@ EMBEDDED = [("H1", (7, 6, 5)), ("H1", (3, 1, 2)), ("H1", (10, 9, 8)), ("HCURL", 
 @pytest.mark.parametrize("space,q", EMBEDDED)
 def test_embedded_route(ctx, space, q):
     """Orders embedded in the uniform kernel of order max p_d (each direction on its
-    own rule, padded with zero-weight points; the submatrix copied out of a scratch
-    buffer) against the oracle and against the per-direction kernel, FP64 and FP32."""
+    own rule, padded with zero-weight points; only the submatrix's entries stored)
+    against the oracle and against the per-direction kernel, FP64 and FP32."""
     say("embedded", space, q)
     assert ctx.aniso_route(space, q) == "embedded"
     assert ctx.aniso_route(space, q, path="general") == "per-direction"
-    assert ctx.aniso_route(space, q, nq=5) == "per-direction"
     n = shapes.dimension(space, q)
     E = 3 if n <= 400 else 2
     X = meshgen.perturbed_hexes(E, seed=700 + sum(q))
