@@ -58,17 +58,20 @@ def rel(G, R):
 @pytest.mark.parametrize("space", SPACES)
 @pytest.mark.parametrize("q", [(1, 2, 3), (3, 1, 2), (2, 4, 1), (1, 1, 1), (3, 3, 2)])
 def test_aniso_vs_oracle(ctx, space, q):
-    say(space, q)
+    """Both routes (the entry point's own, and the per-direction kernel forced) in FP64
+    and FP32 against the oracle."""
+    say(space, q, ctx.aniso_route(space, q))
     E = 3
     X = meshgen.perturbed_hexes(E, seed=600 + sum(q))
-    o64 = run(ctx, space, q, X)
-    o32 = run(ctx, space, q, X, prec="fp32")
-    for e in range(E):
-        R = og.gram(space, q, "trilinear", X[e])
-        fro, mx = rel(elem(o64, e, space, q), R)
-        assert fro <= TOL64 and mx <= TOL64, f"{space} {q} e={e}: fro {fro:.3e} max {mx:.3e}"
-        fro32, _ = rel(elem(o32, e, space, q), R)
-        assert fro32 <= FP32_REL, f"{space} {q} e={e} fp32: {fro32:.3e}"
+    for path in ("auto", "general"):
+        o64 = run(ctx, space, q, X, path=path)
+        o32 = run(ctx, space, q, X, prec="fp32", path=path)
+        for e in range(E):
+            R = og.gram(space, q, "trilinear", X[e])
+            fro, mx = rel(elem(o64, e, space, q), R)
+            assert fro <= TOL64 and mx <= TOL64, f"{space} {q} {path} e={e}: fro {fro:.3e} max {mx:.3e}"
+            fro32, _ = rel(elem(o32, e, space, q), R)
+            assert fro32 <= FP32_REL, f"{space} {q} {path} e={e} fp32: {fro32:.3e}"
 
 
 @pytest.mark.parametrize("space,q", [("H1", (8, 5, 7)), ("HCURL", (6, 4, 5)), ("HDIV", (4, 6, 5)), ("L2", (8, 7, 6)),
