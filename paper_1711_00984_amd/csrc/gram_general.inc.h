@@ -499,6 +499,13 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     const int pg = item / XT, xt = item % XT;
     const int npg = imin(NP, np - pg * NP);
     if (npg <= 0) continue;
+    if constexpr (EMB) {
+      // j2 does not decrease along x in either tiling: a tile whose first x lies past the
+      // embedded orders' j2 range stores nothing
+      int i2 = 0, j2 = 0;
+      decode_x<BC::R2a, DIAG>(sm.xd, xt * 16, i2, j2);
+      if (j2 >= eo.R2b) continue;
+    }
     // ---------------- stage 2: acc2[g] = C2 rows (pair, l) x 16 columns x ----------------
     typename M::acc acc2[BC::NG];
 #pragma unroll
