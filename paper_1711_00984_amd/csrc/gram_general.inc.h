@@ -983,8 +983,8 @@ template <typename Real, bool EMB> constexpr int n_dir_tables() { return EMB ? 3
 // Body of the general-path kernels.  EMB: the orders (p1, p2, p3) <= P embedded in
 // order P (the functions of order p_d in direction d are the first ones of order P: the
 // 1D bases are hierarchical, Sections 2.4 and 2.8.2), each direction with its own rule,
-// and only the column
-// slabs j3 < emb_jmax[b] of component b; the output keeps order P's numbering.
+// only the column slabs j3 < emb_jmax[b] of component b, and the stores write the
+// embedded orders' packed numbering (entries outside it are dropped).
 template <int S, int P, typename Real, bool LISTED, bool EMB>
 __device__ __forceinline__ void general_body(const GeneralArgs& ga) {
   using Sh = Shape<S, P>;
