@@ -203,7 +203,7 @@ int64_t dpg_noalloc_max_elements(void);
  *   DPG_PATH_AUTO: with the default rule (nq = 0), equal orders take the uniform
  *     kernels of dpg_gram_integrate's quadrature path.  Other orders and explicit
  *     rules, where order P = max p_d (raised, for nq > 0, to the order whose default
- *     rule has nq points; P <= 10) carries at most about four times the entries
+ *     rule has nq points; P <= 10) carries at most about 16 times the entries
  *     needed, take the uniform kernels of order P with each direction on its own
  *     rule (zero-weight points pad it to order P's count), storing only the entries
  *     of orders (p1, p2, p3) (the 1D bases are hierarchical, Sections 2.4 and

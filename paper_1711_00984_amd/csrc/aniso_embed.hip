@@ -48,10 +48,11 @@ bool embed_applies(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_op
   int64_t na = 0;
   for (int a = 0; a < ncomp(space); ++a)
     na += int64_t(range1d(space, p[0], a, 0)) * range1d(space, p[1], a, 1) * range1d(space, p[2], a, 2);
-  // the order-P launch computes about (columns / unknowns)^2 times the entries needed;
-  // the uniform kernels run the same sums 5-8x faster than the per-direction kernel
+  // the order-P launch computes about (columns / unknowns)^2 times the entries needed
+  // (less where whole x-tiles fall outside); measured against the per-direction kernel, it
+  // was faster or even up to a squared ratio of 13.8 and slower from 30 on
   const double r = double(emb_columns(space, p, P)) / double(na);
-  return r * r <= 4.0;
+  return r * r <= 16.0;
 }
 
 int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,

@@ -87,7 +87,7 @@ int integrate_aniso(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_g
 
 // Non-uniform orders (or an explicit rule) on the uniform kernels of order max p_d, raised
 // to a default rule of at least nq points (aniso_embed.hip): whether the call takes that
-// route (AUTO path, that order <= 10, and at most about four times the entries needed),
+// route (AUTO path, that order <= 10, and at most about 16 times the entries needed),
 // and the launch.
 bool embed_applies(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_opts& o);
 int integrate_aniso_embed(const dpg_ctx* ctx, int space, const int32_t* p, const dpg_geometry* geom, void* out,
