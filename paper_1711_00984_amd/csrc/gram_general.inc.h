@@ -704,17 +704,21 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     // steps (pi, yc) in order; pipelined (pipe_steps), the MFMAs of the next step are issued
     // before the stores of the current one, so the stores wait on finished accumulators only
     constexpr int NSTEP = NP * YCH;
+    // embedded orders: a y chunk whose first y = (i1, j1) lies past the embedded j1 range
+    // (j1 never decreases along y) stores nothing, and is skipped
+    int ylim = 1 << 30;
+    if constexpr (EMB) ylim = BC::R1a * eo.R1b;
     if constexpr (pipe_steps<S, P, Real>()) {
       Acc ping[YB], pong[YB];
-      mm(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, ping);
+      if (0 < ylim) mm(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{}, ping);
       static_for<NSTEP>([&](auto STEP) {
         constexpr int sp = decltype(STEP)::value, nx = sp + 1;
         if constexpr (nx < NSTEP) {
-          if (nx / YCH < npg)
+          if (nx / YCH < npg && (nx % YCH) * YB * 16 < ylim)
             mm(std::integral_constant<int, nx / YCH>{}, std::integral_constant<int, nx % YCH>{},
                (nx & 1) ? pong : ping);
         }
-        if (sp / YCH < npg) {
+        if (sp / YCH < npg && (sp % YCH) * YB * 16 < ylim) {
           st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{},
              (sp & 1) ? pong : ping);
           if constexpr (sp % YCH == YCH - 1) flush(std::integral_constant<int, sp / YCH>{});
@@ -723,7 +727,7 @@ __device__ __forceinline__ void work(const SmemPtrs& sm, const Regs<S, P, Real, 
     } else {
       static_for<NSTEP>([&](auto STEP) {
         constexpr int sp = decltype(STEP)::value;
-        if (sp / YCH < npg) {
+        if (sp / YCH < npg && (sp % YCH) * YB * 16 < ylim) {
           Acc acc1[YB];
           mm(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);
           st(std::integral_constant<int, sp / YCH>{}, std::integral_constant<int, sp % YCH>{}, acc1);

@@ -142,10 +142,11 @@ def test_explicit_rule_routes(ctx, dpg, space, q, nq):
         assert np.array_equal(u, o)
 
 
-# (8, 4, 4) and (6, 3, 3) skip whole x-tiles (j2 past the embedded range)
+# (8, 4, 4) and (6, 3, 3) skip whole x-tiles (j2 past the embedded range), (4, 8, 4) and
+# L2 (3, 8, 4) whole y chunks (j1 past it)
 EMBEDDED = [("H1", (7, 6, 5)), ("H1", (3, 1, 2)), ("H1", (10, 9, 8)), ("HCURL", (6, 5, 4)), ("HCURL", (2, 3, 1)),
             ("HDIV", (5, 6, 4)), ("HDIV", (4, 4, 2)), ("L2", (8, 7, 6)), ("L2", (3, 2, 1)), ("H1", (8, 4, 4)),
-            ("HDIV", (6, 3, 3))]
+            ("HDIV", (6, 3, 3)), ("H1", (4, 8, 4)), ("L2", (3, 8, 4))]
 
 
 @pytest.mark.parametrize("space,q", EMBEDDED)
